@@ -1,0 +1,178 @@
+"""Pins for the CST-level reference (Algorithms 1, 2, 5-8 and the workload estimate).
+
+Checked against the paper's worked examples (on a fixture graph consistent with
+them), Definition 2 itself, the soundness theorem (all embeddings lie in the
+CST) through brute force and the count oracle, and the partition's promises
+(disjoint, complete, within budget).
+"""
+
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cst_ref
+import bruteforce
+import closed_forms as cf
+from synth import make_graph, query_set
+from test_oracle import random_connected_query, random_tiny_graph
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fig4():
+    d = json.load(open(os.path.join(GOLDEN, "fig4_fixture.json")))
+    g = cf.graph_from_edges(d["n"], [tuple(e) for e in d["edges"]], d["labels"], "fig4")
+    q = cf.query(d["query"]["qlabel"], [tuple(e) for e in d["query"]["qedges"]])
+    return g, q, d["facts"]
+
+
+def test_fig4_tree_shape_and_root():
+    g, q, _ = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    assert cst.root == 0
+    assert cst.parent == [-1, 0, 0, 1]
+    assert cst.nontree == [(1, 2), (2, 3)]
+    assert sorted(cst.cand[0]) == [1, 2]
+    assert sorted(cst.cand[2]) == [6, 7, 8]
+
+
+def test_fig4_workload_example():
+    g, q, facts = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    c, W = cst_ref.workload(cst)
+    f = facts["example_workload"]
+    assert W == f["W"]
+    assert {str(v): x for v, x in c[0].items()} == f["c_u0"]
+    for u, vs in f["leaf_values_one"].items():
+        for v in vs:
+            assert c[int(u[1:])][v] == 1
+
+
+def test_fig4_partition_example():
+    g, q, facts = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    order = [0, 1, 2, 3]
+    parts = cst_ref.partition(cst, order, delta_s=1, force_k=2)
+    f = facts["example_partition"]
+    roots = [sorted(s[0]) for _, s in parts[: len(f["root_parts"])]]
+    # with k = 2 the root split is {v1} | {v2}; further splits only refine below it
+    root_sets = []
+    for _, s in parts:
+        if sorted(s[0]) not in root_sets:
+            root_sets.append(sorted(s[0]))
+    assert root_sets == f["root_parts"]
+    part1 = cst_ref.restricted_sets(cst, order, {0: (0, 1)})
+    for u, vs in f["part1"].items():
+        assert sorted(part1[int(u[1:])]) == vs
+    part2 = cst_ref.restricted_sets(cst, order, {0: (1, 2)})
+    all_rows = cst_ref.enumerate_cst(cst, order)
+    r1 = cst_ref.enumerate_cst(cst, order, part1)
+    r2 = cst_ref.enumerate_cst(cst, order, part2)
+    assert not set(r1) & set(r2)
+    assert sorted(r1 + r2) == all_rows
+    del roots
+
+
+def test_fig4_round_example():
+    g, q, facts = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    f = facts["example_round"]
+    part1 = cst_ref.restricted_sets(cst, f["order"], {0: (0, 1)})
+    P = [tuple(p) for p in f["P"]]
+    P_o, T_v, T_n, B_v, B_n, surv, rest = cst_ref.fast_round(cst, f["order"], P, N_o=64, cand_override=part1)
+    assert [list(p) for p in P_o] == f["P_o"]
+    assert [list(t) for t in T_v] == f["T_v"]
+    assert [list(t) for t in T_n] == f["T_n"]
+    assert B_v == f["B_v"] and B_n == f["B_n"]
+    assert [list(p) for p in surv] == f["survivors"]
+    assert rest == []
+    # a round that cannot take the next p_i whole leaves it in P
+    P_o, *_ , rest = cst_ref.fast_round(cst, f["order"], P, N_o=3, cand_override=part1)
+    assert len(P_o) == 2 and rest == [P[1]]
+
+
+def test_fig4_counts_agree_with_oracle():
+    g, q, _ = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    rows = cst_ref.enumerate_cst(cst, cst_ref.path_order(cst))
+    r = oracle.match(g, q, list_rows=True)
+    assert [tuple(int(x) for x in row) for row in r.rows] == rows
+    assert len(rows) == 3
+
+
+def _check_definition2(g, cst):
+    """Every list is exactly N_G(v) intersected with the neighbour's candidate set."""
+    for (up, u), lists in cst.tree_adj.items():
+        cs = set(cst.cand[u])
+        for vp in cst.cand[up]:
+            want = sorted(int(w) for w in g.neighbors(vp) if int(w) in cs)
+            assert sorted(lists.get(vp, [])) == want
+    for (u, un), lists in cst.nt_adj.items():
+        cs = set(cst.cand[un])
+        for v in cst.cand[u]:
+            assert sorted(lists[v]) == sorted(int(w) for w in g.neighbors(v) if int(w) in cs)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_cst_is_sound_and_complete_on_tiny_graphs(seed):
+    rng = np.random.default_rng(5000 + seed)
+    g = random_tiny_graph(rng)
+    q = random_connected_query(rng, L=int(g.label.max()) + 1)
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    _check_definition2(g, cst)
+    want = bruteforce.embeddings(g, q)
+    # soundness constraint: every embedding's vertices are candidates
+    for row in want:
+        for u, v in enumerate(row):
+            assert v in cst.cand[u]
+    order = cst_ref.path_order(cst)
+    assert cst_ref.enumerate_cst(cst, order) == want
+    # any connected order with parents first gives the same set
+    assert cst_ref.enumerate_cst(cst, cst.bfs) == want
+
+
+def test_cst_on_small_config_matches_oracle_listing():
+    g = make_graph({"kind": "er", "n": 3000, "p": 10 / 2999, "seed": 11, "labels": {"kind": "uniform", "L": 20}})
+    for q in query_set(g, [4] * 8, 21) + query_set(g, [5, 6], 77):
+        cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        _check_definition2(g, cst)
+        r = oracle.match(g, q, list_rows=True)
+        rows = [tuple(int(x) for x in row) for row in r.rows]
+        assert cst_ref.enumerate_cst(cst, cst_ref.path_order(cst)) == rows
+        _, W = cst_ref.workload(cst)
+        assert W >= r.count
+
+
+def test_workload_is_exact_for_distinct_label_trees():
+    g = make_graph({"kind": "er", "n": 2000, "p": 0.004, "seed": 3, "labels": {"kind": "uniform", "L": 6}})
+    rng = np.random.default_rng(12)
+    for _ in range(10):
+        k = int(rng.integers(2, 6))
+        q = random_connected_query(rng, k=k, L=6, extra=0)
+        q.qlabel = rng.choice(6, size=k, replace=False).astype(np.int32)
+        cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        _, W = cst_ref.workload(cst)
+        assert W == oracle.count(g, q) == cf.tree_homomorphism_count(g, q)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_partitions_are_disjoint_complete_and_within_budget(seed):
+    rng = np.random.default_rng(7000 + seed)
+    g = make_graph({"kind": "er", "n": 60, "p": 0.2, "seed": 100 + seed, "labels": {"kind": "uniform", "L": 2}})
+    q = random_connected_query(rng, k=int(rng.integers(2, 6)), L=2, extra=int(rng.integers(0, 3)))
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    order = cst_ref.path_order(cst)
+    full = cst_ref.enumerate_cst(cst, order)
+    budget = cst_ref.image_header_bytes(q.k, len(cst.nontree)) + 200
+    parts = cst_ref.partition(cst, order, delta_s=budget)
+    seen = []
+    for ranges, sets in parts:
+        assert cst_ref.image_bytes(cst, order, sets) <= budget or all(len(s) == 1 for s in sets)
+        seen += cst_ref.enumerate_cst(cst, order, sets)
+    assert len(seen) == len(set(seen))
+    assert sorted(seen) == full
