@@ -1,0 +1,164 @@
+/*
+ * cstm.h -- C ABI of the CST subgraph-matching library (HIP, gfx950).
+ *
+ * The library enumerates or counts every embedding of a small connected query
+ * graph q in a large vertex-labelled data graph G: every map f: V(q) -> V(G)
+ * that is injective, keeps labels and maps each query edge onto an edge of G
+ * (subgraph isomorphism, Section II-A, Definition 1; non-induced; automorphic
+ * images count separately).  It follows the paper's system steps (Section IV):
+ * build a candidate search tree (CST) for q (Section V-A, Algorithm 1),
+ * partition it to an on-chip memory budget (Section V-B, Algorithm 2), and
+ * extend partial embeddings inside each partition (Section VI-A,
+ * Algorithms 4-8).
+ *
+ * Conventions for every call:
+ *   - Every call returns a cstm_status; nothing throws across the ABI.  On an
+ *     error, cstm_last_error() gives a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory.  The caller owns every array
+ *     it passes in; the library never frees caller memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *     that return results to the host synchronise that stream before returning.
+ *   - Handles are not thread-safe: use one handle per thread or lock outside.
+ *   - Vertex ids and labels are int32, CSR offsets int64, counts uint64.
+ */
+#ifndef CSTM_H
+#define CSTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSTM_OK = 0,
+    CSTM_EINVAL = 1,     /* bad argument, malformed graph or query          */
+    CSTM_ENOMEM = 2,     /* an allocation failed                            */
+    CSTM_EDEVICE = 3,    /* a HIP runtime call or kernel failed             */
+    CSTM_ETIMEOUT = 4,   /* reserved: a deadline expired                    */
+    CSTM_EOVERFLOW = 5,  /* listing buffer too small (the count is exact)   */
+    CSTM_ECANCELLED = 6  /* reserved                                        */
+} cstm_status;
+
+#define CSTM_MAX_K 32
+
+typedef struct cstm_ctx cstm_ctx;     /* device, allocator, tuning                  */
+typedef struct cstm_graph cstm_graph; /* resident data graph G and its label index  */
+typedef struct cstm_cst cstm_cst;     /* one query's CST and its partitions         */
+
+/* Device allocator hooks (e.g. a framework's caching allocator).  NULL hooks
+ * mean hipMalloc / hipFree.  alloc returns NULL on failure. */
+typedef void* (*cstm_alloc_fn)(size_t bytes, void* user);
+typedef void (*cstm_free_fn)(void* ptr, void* user);
+
+/* Tuning knobs.  Zero fields take the defaults.
+ *   part_budget_bytes  delta_S of Section V-B: the largest on-chip image a
+ *                      partition may have (LDS bytes, at most the LDS a
+ *                      workgroup can address minus the enumerator's state).
+ *   max_list_len       delta_D of Section V-B: longest candidate list allowed
+ *                      in a partition (0 = no limit).
+ *   waves_per_wg       wavefronts sharing one partition image in LDS (1..16).
+ *   wgs_per_cu         resident enumeration workgroups per compute unit.      */
+typedef struct {
+    uint64_t part_budget_bytes;
+    int32_t max_list_len;
+    int32_t waves_per_wg;
+    int32_t wgs_per_cu;
+    int32_t reserved;
+} cstm_tune;
+
+/* Facts about a built (and possibly partitioned) CST, for reports and tests. */
+typedef struct {
+    int32_t k;                       /* query vertices                              */
+    int32_t root;                    /* root of the BFS tree t_q                    */
+    int32_t parent[CSTM_MAX_K];      /* t_q parent per query vertex (-1 = root)     */
+    int32_t order[CSTM_MAX_K];       /* matching order O (query ids)                */
+    int64_t cand[CSTM_MAX_K];        /* #C(u) per query vertex                      */
+    int64_t tree_entries;            /* total tree-list entries                     */
+    int64_t nontree_entries;         /* total non-tree list entries (one direction) */
+    uint64_t bytes;                  /* device bytes of the CST in HBM              */
+    int32_t d_cst;                   /* longest list (D_CST)                        */
+    int32_t n_nontree;               /* non-tree query edges                        */
+    int64_t n_parts;                 /* partitions (0 before partitioning)          */
+    uint64_t part_bytes;             /* total bytes of all partition images         */
+    uint64_t max_part_bytes;         /* largest partition image                     */
+} cstm_cst_info;
+
+/* Create a context on HIP device `device`.  tune may be NULL (defaults). */
+cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,
+                            const cstm_tune* tune, cstm_ctx** out);
+void cstm_ctx_destroy(cstm_ctx* ctx);
+cstm_status cstm_ctx_get_tune(const cstm_ctx* ctx, cstm_tune* out);
+cstm_status cstm_ctx_set_tune(cstm_ctx* ctx, const cstm_tune* tune);
+/* LDS bytes one workgroup may address on this device. */
+cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out);
+
+/* Load G (Section II-A: undirected, vertex-labelled, simple) as CSR:
+ *   row_ptr[n+1] int64, col[nnz] int32 (nnz = 2|E|, each row sorted ascending,
+ *   no duplicates, no self-loops, symmetric), label[n] int32 >= 0.
+ * on_device = 0: host arrays, copied to the device.  on_device = 1: device
+ * arrays, borrowed (kept alive by the caller until cstm_graph_free).
+ * A device kernel checks the CSR; violations give CSTM_EINVAL.  The call also
+ * builds the label index: vertices grouped by label, each group ordered by
+ * degree descending then id ascending.  n must be < 2^31. */
+cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col, const int32_t* label, int on_device, void* stream,
+                            cstm_graph** out);
+void cstm_graph_free(cstm_graph* g);
+cstm_status cstm_graph_info(const cstm_graph* g, int64_t* n, int64_t* nnz, int32_t* num_labels,
+                            int64_t* max_degree);
+
+/* Build the CST of q (Section V-A, Algorithm 1) on the device.
+ *   k in 1..32, qlabel[k] >= 0, qedges[2*m_q] (host arrays): undirected query
+ *   edges as id pairs; q must be connected, with no self-loop or duplicate edge.
+ * Candidates pass the label/degree filter; the BFS tree t_q is rooted at the
+ * vertex minimising #candidates / query degree; the matching order is the
+ * path-based order of Section V-B. */
+cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
+                           int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out);
+
+/* Partition the CST (Section V-B, Algorithm 2) until every partition's
+ * on-chip image is at most budget_bytes and its longest list at most
+ * max_list_len (0 = no limit); budget_bytes = 0 takes the context's tuning.
+ * Partitions are independent and together hold every embedding exactly once.
+ * *n_parts_out (may be NULL) receives the number of partitions. */
+cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max_list_len,
+                               int64_t* n_parts_out);
+
+cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
+
+/* Copy C(u) (data-vertex ids, candidate order) of query vertex u to host
+ * memory: cap entries at most; *n_out receives #C(u). */
+cstm_status cstm_cst_candidates(const cstm_cst* cst, int32_t u, int32_t* out, int64_t cap, int64_t* n_out);
+
+/* Enumerate the embeddings of a partitioned CST (partitions it first with the
+ * context's tuning if it is not).  list = 0 counts only; list = 1 also writes
+ * rows to the DEVICE buffer rows[cap][k] (row[u] = data vertex of query vertex
+ * u, rows in no particular order).  *count_out receives the exact number of
+ * embeddings; *rows_written min(count, cap).  Returns CSTM_EOVERFLOW when
+ * list = 1 and count > cap. */
+cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap, uint64_t* count_out,
+                           uint64_t* rows_written, void* stream);
+
+/* Enumerate (count) many partitioned CSTs in one persistent launch that draws
+ * partitions from a device work queue.  counts_out[nq] is a host array. */
+cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
+                                 void* stream);
+
+/* Milliseconds spent in the last build / partition / enumerate of this CST,
+ * timed with HIP events on its stream (0 when not run). */
+cstm_status cstm_cst_times(const cstm_cst* cst, double* build_ms, double* partition_ms, double* enumerate_ms);
+
+void cstm_cst_free(cstm_cst* cst);
+
+const char* cstm_last_error(void);
+const char* cstm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSTM_H */

@@ -1,0 +1,177 @@
+// context.hip -- context, device memory, error reporting and scan helpers.
+#include <hipcub/hipcub.hpp>
+
+#include <cstring>
+
+#include "internal.h"
+
+static thread_local std::string g_last_error;
+
+void cstm_set_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" const char* cstm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* cstm_version(void) { return "cstm 0.1 gfx950"; }
+
+// ---------------------------------------------------------------- device memory
+
+void* cstm_ctx::dmalloc(size_t bytes) {
+    void* p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, user);
+        if (!p) throw CstmError{CSTM_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw CstmError{CSTM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
+    }
+    return p;
+}
+
+void cstm_ctx::dfree(void* p) {
+    if (!p) return;
+    if (free_fn) free_fn(p, user);
+    else (void)hipFree(p);
+}
+
+void* cstm_ctx::scratch(size_t bytes) {
+    if (bytes > tmp_bytes) {
+        if (tmp) {
+            (void)hipDeviceSynchronize();
+            dfree(tmp);
+        }
+        tmp = nullptr;
+        tmp_bytes = 0;
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 2;
+        tmp = dmalloc(want);
+        tmp_bytes = want;
+    }
+    return tmp;
+}
+
+void DevArena::release(void* p) {
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        if (blocks[i] == p) {
+            ctx->dfree(p);
+            blocks[i] = blocks.back();
+            blocks.pop_back();
+            return;
+        }
+    }
+}
+
+void DevArena::clear() {
+    if (!ctx) return;
+    for (void* p : blocks) ctx->dfree(p);
+    blocks.clear();
+}
+
+// ---------------------------------------------------------------- scans
+
+template <class T>
+static int64_t exclusive_scan_impl(cstm_ctx* ctx, const T* in, T* out, int64_t n, hipStream_t s) {
+    // out[0..n-1] = exclusive prefix sums, out[n] = total
+    if (n == 0) {
+        T zero = 0;
+        HIP_TRY(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return 0;
+    }
+    size_t tmp_bytes = 0;
+    HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, out + 1, (int)n, s));
+    void* tmp = ctx->scratch(tmp_bytes);
+    HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out + 1, (int)n, s));
+    T zero = 0;
+    HIP_TRY(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
+    T total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, out + n, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return (int64_t)total;
+}
+
+int64_t cstm_exclusive_scan_i64(cstm_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+    CSTM_REQUIRE(n < (int64_t)1 << 31, CSTM_EINVAL, "scan length exceeds 2^31");
+    return exclusive_scan_impl<int64_t>(ctx, in, out, n, s);
+}
+
+int64_t cstm_exclusive_scan_i32(cstm_ctx* ctx, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+    CSTM_REQUIRE(n < (int64_t)1 << 31, CSTM_EINVAL, "scan length exceeds 2^31");
+    return exclusive_scan_impl<int32_t>(ctx, in, out, n, s);
+}
+
+// ---------------------------------------------------------------- context API
+
+static void apply_defaults(cstm_ctx* c) {
+    cstm_tune& t = c->tune;
+    if (t.waves_per_wg <= 0) t.waves_per_wg = 4;
+    if (t.waves_per_wg > 16) t.waves_per_wg = 16;
+    if (t.wgs_per_cu <= 0) t.wgs_per_cu = 4;
+    int64_t state = 256 + (int64_t)t.waves_per_wg * 64;
+    int64_t max_budget = (c->lds_per_wg - state) & ~int64_t(15);
+    if (t.part_budget_bytes == 0) {
+        // share the LDS of one CU between wgs_per_cu workgroups
+        int64_t per = (int64_t)(160 * 1024) / t.wgs_per_cu - state;
+        if (per > max_budget) per = max_budget;
+        t.part_budget_bytes = (uint64_t)(per & ~int64_t(15));
+    }
+    if ((int64_t)t.part_budget_bytes > max_budget) t.part_budget_bytes = (uint64_t)max_budget;
+    if (t.max_list_len < 0) t.max_list_len = 0;
+}
+
+extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,
+                                       const cstm_tune* tune, cstm_ctx** out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(out, CSTM_EINVAL, "out is NULL");
+        *out = nullptr;
+        CSTM_REQUIRE((alloc == nullptr) == (free_fn == nullptr), CSTM_EINVAL, "alloc and free must be given together");
+        int ndev = 0;
+        HIP_TRY(hipGetDeviceCount(&ndev));
+        CSTM_REQUIRE(device >= 0 && device < ndev, CSTM_EINVAL, "device index out of range");
+        HIP_TRY(hipSetDevice(device));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, device));
+        CSTM_REQUIRE(prop.warpSize == CSTM_WAVE, CSTM_EDEVICE, "expected 64-wide wavefronts");
+        cstm_ctx* c = new cstm_ctx();
+        c->device = device;
+        c->alloc = alloc;
+        c->free_fn = free_fn;
+        c->user = user;
+        c->num_cus = prop.multiProcessorCount;
+        c->lds_per_wg = (int64_t)prop.sharedMemPerBlock;
+        if (tune) c->tune = *tune;
+        apply_defaults(c);
+        *out = c;
+    });
+}
+
+extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->dfree(ctx->tmp);
+    delete ctx;
+}
+
+extern "C" cstm_status cstm_ctx_get_tune(const cstm_ctx* ctx, cstm_tune* out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(ctx && out, CSTM_EINVAL, "NULL argument");
+        *out = ctx->tune;
+    });
+}
+
+extern "C" cstm_status cstm_ctx_set_tune(cstm_ctx* ctx, const cstm_tune* tune) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(ctx && tune, CSTM_EINVAL, "NULL argument");
+        ctx->tune = *tune;
+        apply_defaults(ctx);
+    });
+}
+
+extern "C" cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(ctx && out, CSTM_EINVAL, "NULL argument");
+        *out = ctx->lds_per_wg;
+    });
+}

@@ -1,0 +1,392 @@
+// enumerate.hip -- embedding enumeration inside LDS-resident CST partitions
+// (Section VI-A, Algorithms 4-8; buffer bound of Section VI-B).
+//
+// A persistent grid of workgroups pulls partition images from a device queue.
+// Each workgroup copies one image from HBM into LDS with 16-byte loads and
+// its wavefronts extend partial embeddings along the matching order, reading
+// only LDS:
+//   Generator        -- the candidates of the next position are the tree list
+//                       of the parent's mapped candidate, taken 64 at a time,
+//                       one extension per lane (at most N_o = 64 new partial
+//                       results per level and round);
+//   Visited check    -- the lane compares its data vertex with the mapped
+//                       vertices of earlier positions that share its label
+//                       (other labels can never collide);
+//   Edge check       -- for each earlier non-tree neighbour, one bit test in
+//                       the partition's bit row of that neighbour's candidate;
+//   Synchronizer     -- a wavefront ballot keeps the survivors; at the last
+//                       position they are counted (popcount) or written out,
+//                       otherwise they become the next level's frontier.
+// The deepest level with work is always expanded first, so each level holds
+// at most one 64-wide chunk: the frontier is bounded by (k-1) * 64 entries
+// and never leaves the chip.  Level state lives in the wavefront's own
+// registers: lane d holds the state of level d and is read with v_readlane.
+// Work inside a workgroup is shared at the granularity of (root, first child)
+// pairs handed out 64 at a time from an LDS counter.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+struct EnumArgs {
+    const uint64_t* blobs;  // absolute image addresses
+    const int32_t* qids;    // query slot per image (nullptr: slot 0)
+    int64_t n_blobs;
+    unsigned int* head;
+    unsigned long long* counts;
+    int list;
+    int32_t* rows;
+    uint64_t cap;
+    unsigned long long* row_cursor;
+};
+
+__device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
+
+__device__ inline int mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ inline uint32_t rl(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+__device__ inline int32_t rl(int32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ inline uint64_t rl64(uint64_t x, int l) {
+    uint32_t lo = rl((uint32_t)x, l), hi = rl((uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <class T>
+__device__ inline T setl(T cur, T val, int lane, int l) {
+    return lane == l ? val : cur;
+}
+
+// Write complete embeddings of the lanes in `m`; row[u] = data vertex of query vertex u.
+__device__ void emit_rows(const EnumArgs& A, uint64_t m, bool mine, int k, int lane, int32_t pg, uint32_t my_u,
+                          int last_pos, int32_t g_last, int second_pos, int32_t g_second) {
+    if (!m) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0);
+    if (!mine) return;
+    uint64_t idx = base + (uint64_t)mbcnt(m);
+    if (idx >= A.cap) return;
+    int32_t* row = A.rows + idx * (uint64_t)k;
+    for (int i = 0; i < k; ++i) {
+        int32_t val;
+        if (i == last_pos) val = g_last;
+        else if (i == second_pos) val = g_second;
+        else val = rl(pg, i);
+        row[rl(my_u, i)] = val;
+    }
+}
+
+// Enumerate the image in LDS with one wavefront; returns the wavefront's count.
+__device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, const EnumArgs& A) {
+    const int lane = lane_id();
+    const BlobHdr* H = (const BlobHdr*)img;
+    const int k = (int)H->k;
+    const BlobPos* BP = (const BlobPos*)(img + sizeof(BlobHdr));
+    const BlobNt* BN = (const BlobNt*)(img + sizeof(BlobHdr) + (size_t)k * sizeof(BlobPos));
+    // lane d caches the record of position d
+    uint32_t my_n = 0, my_gid = 0, my_toff = 0, my_tadj = 0, my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0;
+    int32_t my_par = -1;
+    if (lane < k) {
+        const BlobPos& P = BP[lane];
+        my_n = P.n;
+        my_gid = P.gid_off;
+        my_toff = P.toff_off;
+        my_tadj = P.tadj_off;
+        my_same = P.same_mask;
+        my_nt = P.nt_mask;
+        my_ntf = P.u_nt_first & 0xFFFFu;
+        my_u = P.u_nt_first >> 16;
+        my_par = P.par;
+    }
+    const uint32_t n0 = rl(my_n, 0);
+    const int32_t* gid0 = (const int32_t*)(img + rl(my_gid, 0));
+    uint64_t cnt = 0;
+
+    if (k == 1) {
+        // every root candidate is an embedding; the first wavefront takes them
+        if (threadIdx.x < CSTM_WAVE) {
+            cnt = n0;
+            if (A.list) {
+                for (uint32_t j0 = 0; j0 < n0; j0 += CSTM_WAVE) {
+                    bool ok = j0 + lane < n0;
+                    uint64_t m = __ballot(ok);
+                    int32_t g = ok ? gid0[j0 + lane] : 0;
+                    emit_rows(A, m, ok, 1, lane, 0, my_u, 0, g, -1, 0);
+                }
+            }
+        }
+        return cnt;
+    }
+
+    const uint32_t* toff1 = (const uint32_t*)(img + rl(my_toff, 1));
+    const uint16_t* tadj1 = (const uint16_t*)(img + rl(my_tadj, 1));
+    const int32_t* gid1 = (const int32_t*)(img + rl(my_gid, 1));
+    const uint32_t E1 = toff1[n0];
+    const bool same01 = rl(my_same, 1) & 1u;
+
+    // level state registers: lane d holds level d
+    int32_t pl = 0, pg = 0;
+    uint32_t lc = 0, le = 0;
+    uint64_t lm = 0;
+
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(s_next, (unsigned int)CSTM_WAVE);
+        t0 = (uint32_t)__shfl((int)t0, 0);
+        if (t0 >= E1) break;
+        const uint32_t t = t0 + lane;
+        const bool valid = t < E1;
+        int32_t r = 0, v1 = 0, g0 = 0, g1 = 0;
+        if (valid) {
+            // root candidate owning list entry t: last r with toff1[r] <= t
+            uint32_t lo = 0, hi = n0;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi + 1) >> 1;
+                if (toff1[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            r = (int32_t)lo;
+            v1 = tadj1[t];
+            g0 = gid0[r];
+            g1 = gid1[v1];
+        }
+        const bool ok1 = valid && !(same01 && g0 == g1);
+        uint64_t m1 = __ballot(ok1);
+        if (k == 2) {
+            cnt += (uint64_t)__popcll(m1);
+            if (A.list) emit_rows(A, m1, ok1, 2, lane, pg, my_u, 1, g1, 0, g0);
+            continue;
+        }
+        while (m1) {
+            const int b = __ffsll((unsigned long long)m1) - 1;
+            m1 &= m1 - 1;
+            const int32_t rb = __shfl(r, b), vb = __shfl(v1, b), g0b = __shfl(g0, b), g1b = __shfl(g1, b);
+            pl = setl(pl, rb, lane, 0);
+            pg = setl(pg, g0b, lane, 0);
+            pl = setl(pl, vb, lane, 1);
+            pg = setl(pg, g1b, lane, 1);
+            // open level 2
+            int d = 2;
+            {
+                const int p = rl(my_par, d);
+                const uint32_t* toff = (const uint32_t*)(img + rl(my_toff, d));
+                const int32_t x = rl(pl, p);
+                lc = setl(lc, toff[x], lane, d);
+                le = setl(le, toff[x + 1], lane, d);
+                lm = setl(lm, (uint64_t)0, lane, d);
+            }
+            for (;;) {
+                uint64_t M = rl64(lm, d);
+                const uint32_t cur = rl(lc, d);
+                const uint16_t* tadj = (const uint16_t*)(img + rl(my_tadj, d));
+                if (M == 0) {
+                    const uint32_t end = rl(le, d);
+                    if (cur >= end) {
+                        if (--d < 2) break;
+                        continue;
+                    }
+                    // Generator: one extension per lane
+                    const uint32_t idx = cur + lane;
+                    const bool val = idx < end;
+                    const int32_t* gid = (const int32_t*)(img + rl(my_gid, d));
+                    const int32_t v = val ? (int32_t)tadj[idx] : 0;
+                    const int32_t g = gid[v];
+                    bool ok = val;
+                    // visited validation: earlier positions with the same label
+                    uint32_t same = rl(my_same, d);
+                    while (same) {
+                        const int j = __ffs(same) - 1;
+                        same &= same - 1;
+                        ok = ok && g != rl(pg, j);
+                    }
+                    // edge validation: one bit per earlier non-tree neighbour
+                    uint32_t ntm = rl(my_nt, d);
+                    uint32_t e = rl(my_ntf, d);
+                    while (ntm) {
+                        const int j = __ffs(ntm) - 1;
+                        ntm &= ntm - 1;
+                        const BlobNt N = BN[e++];
+                        const uint32_t* bits = (const uint32_t*)(img + N.bits_off);
+                        const uint32_t row = (uint32_t)rl(pl, j);
+                        const uint32_t word = bits[row * N.row_words + ((uint32_t)v >> 5)];
+                        ok = ok && ((word >> (v & 31)) & 1u);
+                    }
+                    // Synchronizer
+                    const uint64_t m = __ballot(ok);
+                    lc = setl(lc, cur + (uint32_t)CSTM_WAVE, lane, d);
+                    if (d == k - 1) {
+                        cnt += (uint64_t)__popcll(m);
+                        if (A.list) emit_rows(A, m, ok, k, lane, pg, my_u, d, g, -1, 0);
+                        continue;
+                    }
+                    if (!m) continue;
+                    M = m;
+                }
+                // descend into the lowest surviving lane of the current chunk
+                const int b = __ffsll((unsigned long long)M) - 1;
+                M &= M - 1;
+                lm = setl(lm, M, lane, d);
+                const uint32_t chunk = rl(lc, d) - (uint32_t)CSTM_WAVE;
+                const int32_t v = (int32_t)tadj[chunk + b];
+                const int32_t* gid = (const int32_t*)(img + rl(my_gid, d));
+                pl = setl(pl, v, lane, d);
+                pg = setl(pg, gid[v], lane, d);
+                ++d;
+                const int p = rl(my_par, d);
+                const uint32_t* toff = (const uint32_t*)(img + rl(my_toff, d));
+                const int32_t x = rl(pl, p);
+                lc = setl(lc, toff[x], lane, d);
+                le = setl(le, toff[x + 1], lane, d);
+                lm = setl(lm, (uint64_t)0, lane, d);
+            }
+        }
+    }
+    return cnt;
+}
+
+__global__ void k_enumerate(EnumArgs A) {
+    extern __shared__ uint4 smem_u4[];
+    uint8_t* img = (uint8_t*)smem_u4;
+    __shared__ int64_t s_blob;
+    __shared__ unsigned int s_next;
+    const int lane = lane_id();
+    for (;;) {
+        if (threadIdx.x == 0) s_blob = (int64_t)atomicAdd(A.head, 1u);
+        __syncthreads();
+        const int64_t b = s_blob;
+        if (b >= A.n_blobs) break;
+        const uint8_t* src = (const uint8_t*)A.blobs[b];
+        const uint32_t bytes = ((const BlobHdr*)src)->bytes;
+        for (uint32_t o = threadIdx.x * 16u; o < bytes; o += blockDim.x * 16u)
+            *(uint4*)(img + o) = *(const uint4*)(src + o);
+        if (threadIdx.x == 0) s_next = 0;
+        __syncthreads();
+        const uint64_t c = enumerate_image(img, &s_next, A);
+        if (lane == 0 && c) atomicAdd(&A.counts[A.qids ? A.qids[b] : 0], (unsigned long long)c);
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
+                        uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
+    int64_t total = 0;
+    uint64_t max_blob = 0;
+    int kq = 0;
+    for (int q = 0; q < nq; ++q) {
+        cstm_cst* c = csts[q];
+        if (!c->partitioned) cstm_partition_run(c, 0, ctx->tune.max_list_len);
+        total += c->n_parts;
+        max_blob = std::max<uint64_t>(max_blob, c->max_blob);
+        kq = c->k;
+    }
+    DevArena mem;
+    mem.ctx = ctx;
+    unsigned long long* counts = mem.get_n<unsigned long long>(nq + 2);
+    HIP_TRY(hipMemsetAsync(counts, 0, (nq + 2) * sizeof(unsigned long long), s));
+    unsigned int* head = (unsigned int*)(counts + nq);
+    unsigned long long* row_cursor = counts + nq + 1;
+    if (total > 0) {
+        CSTM_REQUIRE(total < ((int64_t)1 << 32) - 1, CSTM_EINVAL, "too many partitions for one launch");
+        const uint64_t* blobs;
+        const int32_t* qids = nullptr;
+        if (nq == 1) {
+            blobs = csts[0]->blob_off;
+        } else {
+            uint64_t* bl = mem.get_n<uint64_t>(total);
+            int32_t* qi = mem.get_n<int32_t>(total);
+            std::vector<int32_t> hq(total);
+            int64_t o = 0;
+            for (int q = 0; q < nq; ++q) {
+                int64_t n = csts[q]->n_parts;
+                if (!n) continue;
+                HIP_TRY(hipMemcpyAsync(bl + o, csts[q]->blob_off, n * 8, hipMemcpyDeviceToDevice, s));
+                std::fill(hq.begin() + o, hq.begin() + o + n, q);
+                o += n;
+            }
+            HIP_TRY(hipMemcpyAsync(qi, hq.data(), total * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            blobs = bl;
+            qids = qi;
+        }
+        EnumArgs A;
+        A.blobs = blobs;
+        A.qids = qids;
+        A.n_blobs = total;
+        A.head = head;
+        A.counts = counts;
+        A.list = list;
+        A.rows = rows;
+        A.cap = cap;
+        A.row_cursor = row_cursor;
+        const int waves = ctx->tune.waves_per_wg;
+        const size_t lds = (size_t)cstm_align16(max_blob);
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void*)k_enumerate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)ctx->lds_per_wg - 64);
+            (void)hipGetLastError();
+            attr_set = true;
+        }
+        int64_t grid = (int64_t)ctx->num_cus * ctx->tune.wgs_per_cu;
+        grid = std::min<int64_t>(grid, total);
+        k_enumerate<<<(unsigned)grid, waves * CSTM_WAVE, lds, s>>>(A);
+        HIP_TRY(hipGetLastError());
+    }
+    std::vector<unsigned long long> h(nq + 2);
+    HIP_TRY(hipMemcpyAsync(h.data(), counts, (nq + 2) * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int q = 0; q < nq; ++q) counts_host[q] = h[q];
+    if (rows_written) *rows_written = std::min<uint64_t>(h[nq + 1], cap);
+    (void)kq;
+}
+
+extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap, uint64_t* count_out,
+                                      uint64_t* rows_written, void* stream) {
+    uint64_t count = 0;
+    uint64_t written = 0;
+    cstm_status st = cstm_guard([&] {
+        CSTM_REQUIRE(cst, CSTM_EINVAL, "NULL cst");
+        CSTM_REQUIRE(!list || rows || cap == 0, CSTM_EINVAL, "listing needs a row buffer");
+        HIP_TRY(hipSetDevice(cst->ctx->device));
+        hipStream_t s = stream ? (hipStream_t)stream : cst->stream;
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        HIP_TRY(hipEventRecord(a, s));
+        cstm_cst* one[1] = {cst};
+        cstm_enumerate_run(cst->ctx, 1, one, list, rows, cap, &count, &written, s);
+        HIP_TRY(hipEventRecord(b, s));
+        HIP_TRY(hipEventSynchronize(b));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        cst->t_enum = ms;
+    });
+    if (count_out) *count_out = count;
+    if (rows_written) *rows_written = written;
+    if (st == CSTM_OK && list && count > cap) {
+        cstm_set_error("row buffer smaller than the number of embeddings");
+        return CSTM_EOVERFLOW;
+    }
+    return st;
+}
+
+extern "C" cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
+                                            void* stream) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(ctx && (nq == 0 || (csts && counts_out)), CSTM_EINVAL, "NULL argument");
+        CSTM_REQUIRE(nq >= 0, CSTM_EINVAL, "negative query count");
+        for (int q = 0; q < nq; ++q) CSTM_REQUIRE(csts[q] && csts[q]->ctx == ctx, CSTM_EINVAL, "bad CST handle");
+        if (nq == 0) return;
+        HIP_TRY(hipSetDevice(ctx->device));
+        cstm_enumerate_run(ctx, nq, csts, 0, nullptr, 0, counts_out, nullptr, (hipStream_t)stream);
+    });
+}

@@ -1,0 +1,334 @@
+"""ctypes binding of ``libcstm.so`` (see ``include/cstm.h``).
+
+Argument marshalling only: every step of the matching path runs in the HIP
+library.  PyTorch provides device memory and streams.  Loading fails with an
+ImportError when the library has not been built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcstm.so")
+
+MAX_K = 32
+
+OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, EOVERFLOW, ECANCELLED = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ETIMEOUT", 5: "EOVERFLOW", 6: "ECANCELLED"}
+
+
+class CstmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cstm_tune(ctypes.Structure):
+    _fields_ = [
+        ("part_budget_bytes", ctypes.c_uint64),
+        ("max_list_len", ctypes.c_int32),
+        ("waves_per_wg", ctypes.c_int32),
+        ("wgs_per_cu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class cstm_cst_info(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("root", ctypes.c_int32),
+        ("parent", ctypes.c_int32 * MAX_K),
+        ("order", ctypes.c_int32 * MAX_K),
+        ("cand", ctypes.c_int64 * MAX_K),
+        ("tree_entries", ctypes.c_int64),
+        ("nontree_entries", ctypes.c_int64),
+        ("bytes", ctypes.c_uint64),
+        ("d_cst", ctypes.c_int32),
+        ("n_nontree", ctypes.c_int32),
+        ("n_parts", ctypes.c_int64),
+        ("part_bytes", ctypes.c_uint64),
+        ("max_part_bytes", ctypes.c_uint64),
+    ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+EXPORTS = [
+    "cstm_ctx_create", "cstm_ctx_destroy", "cstm_ctx_get_tune", "cstm_ctx_set_tune", "cstm_ctx_lds_bytes",
+    "cstm_graph_load", "cstm_graph_free", "cstm_graph_info",
+    "cstm_cst_build", "cstm_cst_partition", "cstm_cst_info_get", "cstm_cst_candidates",
+    "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
+    "cstm_last_error", "cstm_version",
+]
+
+_lib = None
+
+
+def load_library():
+    """Load ``libcstm.so``; raises ImportError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2102_10768_amd.build`")
+    # PyTorch ships its own HIP runtime with the same soname as the system one.
+    # Loading torch first makes the library bind to that runtime, so one process
+    # never holds two HIP runtimes (the second would see no device).
+    import torch  # noqa: F401
+
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    st = ctypes.c_int
+    sig = {
+        "cstm_ctx_create": (st, [ctypes.c_int, ALLOC_FN, FREE_FN, P, ctypes.POINTER(cstm_tune), ctypes.POINTER(P)]),
+        "cstm_ctx_destroy": (None, [P]),
+        "cstm_ctx_get_tune": (st, [P, ctypes.POINTER(cstm_tune)]),
+        "cstm_ctx_set_tune": (st, [P, ctypes.POINTER(cstm_tune)]),
+        "cstm_ctx_lds_bytes": (st, [P, ctypes.POINTER(I64)]),
+        "cstm_graph_load": (st, [P, I64, I64, P, P, P, ctypes.c_int, P, ctypes.POINTER(P)]),
+        "cstm_graph_free": (None, [P]),
+        "cstm_graph_info": (st, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I64)]),
+        "cstm_cst_build": (st, [P, P, I32, P, I32, P, P, ctypes.POINTER(P)]),
+        "cstm_cst_partition": (st, [P, U64, I32, ctypes.POINTER(I64)]),
+        "cstm_cst_info_get": (st, [P, ctypes.POINTER(cstm_cst_info)]),
+        "cstm_cst_candidates": (st, [P, I32, P, I64, ctypes.POINTER(I64)]),
+        "cstm_enumerate": (st, [P, ctypes.c_int, P, U64, ctypes.POINTER(U64), ctypes.POINTER(U64), P]),
+        "cstm_batch_enumerate": (st, [P, I32, P, P, P]),
+        "cstm_cst_times": (st, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]),
+        "cstm_cst_free": (None, [P]),
+        "cstm_last_error": (ctypes.c_char_p, []),
+        "cstm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        msg = load_library().cstm_last_error().decode(errors="replace")
+        raise CstmError(status, msg)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- thin object wrappers
+
+
+class Context:
+    """A device context (``cstm_ctx_create``).  ``tune`` is a dict of cstm_tune fields."""
+
+    def __init__(self, device: int = 0, tune: dict | None = None, torch_allocator: bool = False):
+        lib = load_library()
+        self._keep = []
+        alloc = ALLOC_FN()
+        free = FREE_FN()
+        if torch_allocator:
+            import torch
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            alloc, free = ALLOC_FN(_alloc), FREE_FN(_free)
+            self._keep += [alloc, free]
+        t = cstm_tune(**(tune or {}))
+        h = ctypes.c_void_p()
+        _check(lib.cstm_ctx_create(device, alloc, free, None, ctypes.byref(t), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    @property
+    def tune(self) -> dict:
+        t = cstm_tune()
+        _check(load_library().cstm_ctx_get_tune(self.handle, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in cstm_tune._fields_}
+
+    @tune.setter
+    def tune(self, values: dict):
+        cur = self.tune
+        cur.update(values)
+        t = cstm_tune(**cur)
+        _check(load_library().cstm_ctx_set_tune(self.handle, ctypes.byref(t)))
+
+    def lds_bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().cstm_ctx_lds_bytes(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().cstm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A resident data graph (``cstm_graph_load``).
+
+    Pass torch CUDA tensors (borrowed: the tensors are kept referenced here) or
+    numpy / CPU arrays (copied to the device).
+    """
+
+    def __init__(self, ctx: Context, row_ptr, col, label, stream=None):
+        lib = load_library()
+        self.ctx = ctx
+        on_device = _is_cuda(row_ptr)
+        if on_device:
+            import torch
+
+            self._tensors = (row_ptr.contiguous(), col.contiguous(), label.contiguous())
+            assert self._tensors[0].dtype == torch.int64 and self._tensors[1].dtype == torch.int32
+            ptrs = [t.data_ptr() for t in self._tensors]
+            n = self._tensors[2].numel()
+            nnz = self._tensors[1].numel()
+        else:
+            self._tensors = (
+                np.ascontiguousarray(row_ptr, dtype=np.int64),
+                np.ascontiguousarray(col, dtype=np.int32),
+                np.ascontiguousarray(label, dtype=np.int32),
+            )
+            ptrs = [a.ctypes.data for a in self._tensors]
+            n = self._tensors[2].shape[0]
+            nnz = self._tensors[1].shape[0]
+        h = ctypes.c_void_p()
+        _check(lib.cstm_graph_load(ctx.handle, n, nnz, ptrs[0], ptrs[1], ptrs[2], int(on_device),
+                                   _stream_ptr(stream) if on_device else None, ctypes.byref(h)))
+        self.handle = h
+        if not on_device:
+            self._tensors = None
+
+    def info(self) -> dict:
+        n, nnz, L, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(load_library().cstm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(L),
+                                              ctypes.byref(md)))
+        return {"n": n.value, "nnz": nnz.value, "num_labels": L.value, "max_degree": md.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().cstm_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CST:
+    """One query's candidate search tree (``cstm_cst_build``)."""
+
+    def __init__(self, ctx: Context, graph: Graph, qlabel, qedges, stream=None):
+        lib = load_library()
+        self.ctx, self.graph = ctx, graph
+        ql = np.ascontiguousarray(qlabel, dtype=np.int32)
+        qe = np.ascontiguousarray(np.asarray(qedges, dtype=np.int32).reshape(-1, 2))
+        self.k = int(ql.shape[0])
+        h = ctypes.c_void_p()
+        _check(lib.cstm_cst_build(ctx.handle, graph.handle, self.k, ql.ctypes.data, int(qe.shape[0]),
+                                  qe.ctypes.data if qe.size else None, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def partition(self, budget_bytes: int = 0, max_list_len: int = 0) -> int:
+        n = ctypes.c_int64()
+        _check(load_library().cstm_cst_partition(self.handle, int(budget_bytes), int(max_list_len), ctypes.byref(n)))
+        return n.value
+
+    def info(self) -> dict:
+        i = cstm_cst_info()
+        _check(load_library().cstm_cst_info_get(self.handle, ctypes.byref(i)))
+        k = i.k
+        return {
+            "k": k, "root": i.root, "parent": list(i.parent[:k]), "order": list(i.order[:k]),
+            "cand": list(i.cand[:k]), "tree_entries": i.tree_entries, "nontree_entries": i.nontree_entries,
+            "bytes": i.bytes, "d_cst": i.d_cst, "n_nontree": i.n_nontree, "n_parts": i.n_parts,
+            "part_bytes": i.part_bytes, "max_part_bytes": i.max_part_bytes,
+        }
+
+    def candidates(self, u: int) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_int64()
+        _check(lib.cstm_cst_candidates(self.handle, u, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        _check(lib.cstm_cst_candidates(self.handle, u, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out
+
+    def count(self, stream=None) -> int:
+        c, w = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load_library().cstm_enumerate(self.handle, 0, None, 0, ctypes.byref(c), ctypes.byref(w),
+                                             _stream_ptr(stream)))
+        return c.value
+
+    def list(self, cap: int, stream=None):
+        """Returns (count, rows) with rows a (min(count, cap), k) int32 CUDA tensor; raises on overflow."""
+        import torch
+
+        rows = torch.empty((max(cap, 1), self.k), dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+        c, w = ctypes.c_uint64(), ctypes.c_uint64()
+        st = load_library().cstm_enumerate(self.handle, 1, rows.data_ptr(), int(cap), ctypes.byref(c),
+                                           ctypes.byref(w), _stream_ptr(stream))
+        _check(st)
+        return c.value, rows[: w.value]
+
+    def times(self) -> dict:
+        b, p, e = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().cstm_cst_times(self.handle, ctypes.byref(b), ctypes.byref(p), ctypes.byref(e)))
+        return {"build_ms": b.value, "partition_ms": p.value, "enumerate_ms": e.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().cstm_cst_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_count(ctx: Context, csts: list, stream=None) -> list[int]:
+    """``cstm_batch_enumerate``: counts of many partitioned CSTs from one persistent launch."""
+    n = len(csts)
+    arr = (ctypes.c_void_p * max(n, 1))(*[c.handle.value for c in csts])
+    out = (ctypes.c_uint64 * max(n, 1))()
+    _check(load_library().cstm_batch_enumerate(ctx.handle, n, arr, out, _stream_ptr(stream)))
+    return [int(out[i]) for i in range(n)]
+
+
+def _is_cuda(x) -> bool:
+    try:
+        import torch
+
+        return isinstance(x, torch.Tensor) and x.is_cuda
+    except ImportError:
+        return False

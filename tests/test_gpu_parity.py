@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path against the CPU oracle (bit-exact counts and sorted lists).
+
+Every test calls through the C ABI (ctypes binding).  Expected values come from
+``oracle`` (and, for CST contents, from ``oracle.cst_ref``) on the same seeded
+inputs.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cst_ref
+import closed_forms as cf
+from synth import make_graph, query_set
+from test_oracle import random_connected_query, random_tiny_graph
+from gpu_common import ctx, gpu_count, gpu_graph, gpu_rows
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_rows(g, q):
+    r = oracle.match(g, q, list_rows=True, cap=1 << 22)
+    assert r.status == oracle.OK
+    return r.count, [tuple(int(x) for x in row) for row in r.rows]
+
+
+def test_library_loads_and_reports_device():
+    from paper_2102_10768_amd import cstm
+
+    lib = cstm.load_library()
+    assert b"gfx950" in lib.cstm_version()
+    assert ctx().lds_bytes() >= 64 * 1024
+
+
+def test_fig4_fixture_matches_reference_and_oracle():
+    d = json.load(open(os.path.join(GOLDEN, "fig4_fixture.json")))
+    g = cf.graph_from_edges(d["n"], [tuple(e) for e in d["edges"]], d["labels"], "fig4")
+    q = cf.query(d["query"]["qlabel"], [tuple(e) for e in d["query"]["qedges"]])
+    say("fig4: load")
+    G = gpu_graph(g)
+    from paper_2102_10768_amd import cstm
+
+    say("fig4: build")
+    c = cstm.CST(ctx(), G, q.qlabel, q.qedges)
+    ref = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    info = c.info()
+    assert info["root"] == ref.root
+    assert info["parent"] == ref.parent
+    assert info["order"] == cst_ref.path_order(ref)
+    for u in range(q.k):
+        assert c.candidates(u).tolist() == ref.cand[u]
+    say("fig4: enumerate")
+    n, rows = c.list(64)
+    want_n, want_rows = _oracle_rows(g, q)
+    assert n == want_n == 3
+    assert sorted(tuple(int(x) for x in r) for r in rows.cpu().numpy()) == want_rows
+    c.close()
+
+
+def _c1():
+    return make_graph({"kind": "er", "n": 3000, "p": 10 / 2999, "seed": 11, "labels": {"kind": "uniform", "L": 20}})
+
+
+def test_small_config_counts_and_lists():
+    g = _c1()
+    G = gpu_graph(g)
+    for i, q in enumerate(query_set(g, [4] * 8, 21)):
+        say(f"small config query {i}: labels {q.qlabel.tolist()} edges {q.qedges.tolist()}")
+        want_n, want_rows = _oracle_rows(g, q)
+        n, rows = gpu_rows(G, q)
+        assert n == want_n
+        assert rows == want_rows
+
+
+def test_candidate_sets_match_reference():
+    g = _c1()
+    G = gpu_graph(g)
+    from paper_2102_10768_amd import cstm
+
+    for q in query_set(g, [4, 5, 6, 7] * 2, 55):
+        ref = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        c = cstm.CST(ctx(), G, q.qlabel, q.qedges)
+        info = c.info()
+        assert info["root"] == ref.root and info["parent"] == ref.parent
+        assert info["order"] == cst_ref.path_order(ref)
+        for u in range(q.k):
+            assert c.candidates(u).tolist() == ref.cand[u]
+        assert info["tree_entries"] == sum(len(l) for lists in ref.tree_adj.values() for l in lists.values())
+        c.close()
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_tiny_graphs(seed):
+    rng = np.random.default_rng(1000 + seed)
+    g = random_tiny_graph(rng)
+    q = random_connected_query(rng, L=int(g.label.max()) + 1)
+    say(f"tiny seed {seed}: n={g.n} k={q.k} m_q={q.m_q}")
+    G = gpu_graph(g)
+    want_n, want_rows = _oracle_rows(g, q)
+    n, rows = gpu_rows(G, q)
+    assert n == want_n
+    assert rows == want_rows
+
+
+def test_partition_budget_does_not_change_results():
+    g = make_graph({"kind": "chung_lu", "n": 5000, "m": 40000, "gamma": 2.3, "seed": 31,
+                    "labels": {"kind": "zipf", "L": 8, "s": 1.0}})
+    G = gpu_graph(g)
+    qs = query_set(g, [4, 5, 6], 32)
+    for q in qs:
+        r = oracle.match(g, q, node_budget=5 * 10**8)
+        if r.status != oracle.OK:
+            continue
+        counts = []
+        for budget in (0, 16384, 4096, 1024):
+            n, info = gpu_count(G, q, budget)
+            say(f"budget {budget}: count {n} parts {info['n_parts']} max {info['max_part_bytes']}")
+            counts.append(n)
+            if budget:
+                assert info["max_part_bytes"] <= budget
+        assert counts == [r.count] * len(counts)
+
+
+def test_partition_count_matches_reference_rule():
+    g = make_graph({"kind": "er", "n": 300, "p": 0.05, "seed": 9, "labels": {"kind": "uniform", "L": 3}})
+    G = gpu_graph(g)
+    for q in query_set(g, [3, 4, 5], 10):
+        ref = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        order = cst_ref.path_order(ref)
+        for budget in (2048, 512):
+            parts = cst_ref.partition(ref, order, delta_s=budget)
+            n, info = gpu_count(G, q, budget)
+            assert info["n_parts"] == len(parts)
+            assert n == oracle.count(g, q)
+
+
+def test_edge_cases_single_vertex_absent_label_and_k2():
+    g = _c1()
+    G = gpu_graph(g)
+    for lab in (0, 7, 19):
+        n, _ = gpu_count(G, cf.query([lab], []))
+        assert n == int((g.label == lab).sum())
+    n, _ = gpu_count(G, cf.query([99], []))
+    assert n == 0
+    n, _ = gpu_count(G, cf.query([0, 99, 1], [(0, 1), (1, 2)]))
+    assert n == 0
+    for la, lb in [(0, 1), (3, 3)]:
+        q = cf.query([la, lb], [(0, 1)])
+        want_n, want_rows = _oracle_rows(g, q)
+        n, rows = gpu_rows(G, q)
+        assert n == want_n and rows == want_rows
+
+
+def test_closed_forms_on_gpu():
+    from math import perm
+
+    G = gpu_graph(cf.complete(9))
+    for k in range(1, 7):
+        n, _ = gpu_count(G, cf.clique_query([0] * k))
+        assert n == perm(9, k)
+    G = gpu_graph(cf.complete_bipartite(4, 5))
+    assert gpu_count(G, cf.cycle_query(3))[0] == 0
+    assert gpu_count(G, cf.cycle_query(4))[0] == cf.c4_in_complete_bipartite(4, 5)
+
+
+def test_batch_matches_individual_counts():
+    g = _c1()
+    G = gpu_graph(g)
+    from paper_2102_10768_amd import cstm
+
+    qs = query_set(g, [3, 4, 5, 6] * 3, 71)
+    csts = [cstm.CST(ctx(), G, q.qlabel, q.qedges) for q in qs]
+    for c in csts:
+        c.partition(4096)
+    got = cstm.batch_count(ctx(), csts)
+    want = [oracle.count(g, q) for q in qs]
+    assert got == want
+    for c in csts:
+        c.close()
+
+
+def test_malformed_inputs_rejected():
+    from paper_2102_10768_amd import cstm
+
+    g = cf.graph_from_edges(4, [(0, 1), (1, 2)], [0, 0, 0, 0])
+    bad_col = g.col.copy()
+    bad_col[0] = 3  # row 0 now points at 3, but 3 does not point back
+    with pytest.raises(cstm.CstmError):
+        cstm.Graph(ctx(), g.row_ptr, bad_col, g.label)
+    G = gpu_graph(g)
+    with pytest.raises(cstm.CstmError):
+        cstm.CST(ctx(), G, [0, 0, 0], [(0, 1)])  # disconnected
+    with pytest.raises(cstm.CstmError):
+        cstm.CST(ctx(), G, [0, 0], [(0, 0)])  # self-loop
