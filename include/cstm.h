@@ -38,7 +38,7 @@ typedef enum {
     CSTM_EINVAL = 1,     /* bad argument, malformed graph or query          */
     CSTM_ENOMEM = 2,     /* an allocation failed                            */
     CSTM_EDEVICE = 3,    /* a HIP runtime call or kernel failed             */
-    CSTM_ETIMEOUT = 4,   /* reserved: a deadline expired                    */
+    CSTM_ETIMEOUT = 4,   /* a deadline expired (no count is reported)       */
     CSTM_EOVERFLOW = 5,  /* listing buffer too small (the count is exact)   */
     CSTM_ECANCELLED = 6  /* reserved                                        */
 } cstm_status;
@@ -61,14 +61,62 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *   max_list_len       delta_D of Section V-B: longest candidate list allowed
  *                      in a partition (0 = no limit).
  *   waves_per_wg       wavefronts sharing one partition image in LDS (1..16).
- *   wgs_per_cu         resident enumeration workgroups per compute unit.      */
+ *   wgs_per_cu         resident enumeration workgroups per compute unit.
+ *   collect_stats      1: enumeration launches also count the work they do
+ *                      (cstm_enum_stats); 0: they do not.
+ *   enum_mode          where enumeration reads the CST from:
+ *                        CSTM_MODE_LDS  partitions staged into LDS (the
+ *                                       on-chip matcher of Section VI),
+ *                        CSTM_MODE_HBM  the whole CST from device memory
+ *                                       (L2-resident), with wavefronts sharing
+ *                                       work through a device task queue,
+ *                        CSTM_MODE_AUTO LDS for CSTs the caller partitioned
+ *                                       (cstm_cst_partition), else HBM.
+ *   max_replication    reserved (limit on partition bytes / CST bytes).
+ *   deadline_ms        HBM mode: stop an enumeration launch after this many
+ *                      milliseconds and return CSTM_ETIMEOUT (0 = no limit).
+ *   hbm_wgs_per_cu     HBM mode: 256-thread workgroups per compute unit.
+ *   hbm_donate_period  HBM mode: chunks a wavefront expands between checks
+ *                      for waiting wavefronts (negative: never donate).      */
+#define CSTM_MODE_AUTO 0
+#define CSTM_MODE_LDS 1
+#define CSTM_MODE_HBM 2
 typedef struct {
     uint64_t part_budget_bytes;
     int32_t max_list_len;
     int32_t waves_per_wg;
     int32_t wgs_per_cu;
+    int32_t collect_stats;
+    int32_t enum_mode;
+    int32_t max_replication;
+    int32_t deadline_ms;
+    int32_t hbm_wgs_per_cu;
+    int32_t hbm_donate_period;
     int32_t reserved;
 } cstm_tune;
+
+/* What the last enumeration launch on a context did (Section VI-B's counts).
+ *   kernel_ms      duration of the enumeration kernel(s) alone (HIP events
+ *                  on the stream, around each launch);
+ *   images         LDS mode: partition images processed; HBM mode: tasks run;
+ *   image_bytes    LDS mode: bytes staged from HBM into LDS; HBM mode: tasks
+ *                  donated by busy wavefronts to idle ones;
+ *   extensions     N: new partial results generated (one per lane per valid
+ *                  candidate, all levels after the root);
+ *   edge_checks    M: non-tree edge validations executed;
+ *   pushed         F: surviving partial results that were extended further.
+ * The work counters are zero unless tune.collect_stats was set. */
+typedef struct {
+    double kernel_ms;
+    int32_t mode;        /* CSTM_MODE_LDS or CSTM_MODE_HBM (last launch)   */
+    int32_t launches;
+    uint64_t images;
+    uint64_t image_bytes;
+    uint64_t extensions;
+    uint64_t edge_checks;
+    uint64_t pushed;
+    double busy_frac;    /* HBM mode: share of wavefront time spent expanding  */
+} cstm_enum_stats;
 
 /* Facts about a built (and possibly partitioned) CST, for reports and tests. */
 typedef struct {
@@ -147,6 +195,10 @@ cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap,
  * partitions from a device work queue.  counts_out[nq] is a host array. */
 cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
                                  void* stream);
+
+/* Statistics of the last enumeration launch (cstm_enumerate or
+ * cstm_batch_enumerate) made with this context. */
+cstm_status cstm_ctx_last_enum_stats(const cstm_ctx* ctx, cstm_enum_stats* out);
 
 /* Milliseconds spent in the last build / partition / enumerate of this CST,
  * timed with HIP events on its stream (0 when not run). */

@@ -118,6 +118,11 @@ static void apply_defaults(cstm_ctx* c) {
     }
     if ((int64_t)t.part_budget_bytes > max_budget) t.part_budget_bytes = (uint64_t)max_budget;
     if (t.max_list_len < 0) t.max_list_len = 0;
+    if (t.max_replication == 0) t.max_replication = 16;  // negative: no limit
+    if (t.enum_mode < CSTM_MODE_AUTO || t.enum_mode > CSTM_MODE_HBM) t.enum_mode = CSTM_MODE_AUTO;
+    if (t.deadline_ms < 0) t.deadline_ms = 0;
+    if (t.hbm_wgs_per_cu <= 0) t.hbm_wgs_per_cu = 4;
+    if (t.hbm_donate_period == 0) t.hbm_donate_period = 64;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,
@@ -151,6 +156,7 @@ extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->dfree(ctx->tmp);
+    ctx->dfree(ctx->enum_ws);
     delete ctx;
 }
 
@@ -173,5 +179,12 @@ extern "C" cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out) {
     return cstm_guard([&] {
         CSTM_REQUIRE(ctx && out, CSTM_EINVAL, "NULL argument");
         *out = ctx->lds_per_wg;
+    });
+}
+
+extern "C" cstm_status cstm_ctx_last_enum_stats(const cstm_ctx* ctx, cstm_enum_stats* out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(ctx && out, CSTM_EINVAL, "NULL argument");
+        *out = ctx->last_enum;
     });
 }

@@ -158,7 +158,7 @@ __global__ void k_list_count(const int32_t* __restrict__ pc, int64_t np, const i
 __global__ void k_list_fill(const int32_t* __restrict__ pc, int64_t np, const int64_t* __restrict__ row_ptr,
                             const int32_t* __restrict__ col, const uint64_t* __restrict__ lab_rank, uint64_t key,
                             int64_t cnt0, const int32_t* __restrict__ loc, const int64_t* __restrict__ off,
-                            int32_t* __restrict__ adj) {
+                            int32_t* __restrict__ adj, int32_t* __restrict__ adj_gid) {
     const int lane = lane_id();
     for (int64_t i = global_wave(); i < np; i += num_waves()) {
         int32_t v = pc[i];
@@ -166,13 +166,17 @@ __global__ void k_list_fill(const int32_t* __restrict__ pc, int64_t np, const in
         int64_t out = off[i];
         for (int64_t j0 = b; j0 < e; j0 += CSTM_WAVE) {
             int64_t j = j0 + lane;
-            int32_t idx = -1;
+            int32_t idx = -1, w = 0;
             if (j < e) {
-                uint64_t d = lab_rank[col[j]] - key;
+                w = col[j];
+                uint64_t d = lab_rank[w] - key;
                 if (d < (uint64_t)cnt0) idx = loc[d];
             }
             uint64_t m = ballot(idx >= 0);
-            if (idx >= 0) adj[out + mbcnt(m)] = idx;
+            if (idx >= 0) {
+                adj[out + mbcnt(m)] = idx;
+                if (adj_gid) adj_gid[out + mbcnt(m)] = w;
+            }
             out += __popcll(m);
         }
     }
@@ -287,7 +291,7 @@ struct EventTimer {
 
 // The lists of `from` (a query vertex) into `to`, using to's rank table.
 static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, EdgeLists& el, int* d_max,
-                        int64_t* d_cnt) {
+                        int64_t* d_cnt, bool with_gid) {
     const cstm_graph* g = c->g;
     hipStream_t s = c->stream;
     const int64_t np = c->ncand[from];
@@ -301,9 +305,10 @@ static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, Edge
     }
     el.entries = cstm_exclusive_scan_i64(c->ctx, d_cnt, el.off, np, s);
     el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
+    if (with_gid) el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
     if (np && el.entries) {
         k_list_fill<<<wave_grid(np), kWaveBlock, 0, s>>>(c->cand[from], np, g->row_ptr, g->col, g->lab_rank, key,
-                                                         c->cnt0[to], loc[to], el.off, el.adj);
+                                                         c->cnt0[to], loc[to], el.off, el.adj, el.adj_gid);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipMemcpyAsync(&el.max_len, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -423,7 +428,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     if (!c->empty) {
         for (int t = 1; t < k; ++t) {
             int u = c->bfs[t];
-            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max, d_cnt);
+            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max, d_cnt, false);
             c->d_cst = std::max(c->d_cst, c->tree[u].max_len);
         }
     }
@@ -485,7 +490,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.from = c->pos_of[a];
         el.to = c->pos_of[b];
         if (!c->empty) {
-            build_lists(c, a, b, loc, el, d_max, d_cnt);
+            build_lists(c, a, b, loc, el, d_max, d_cnt, true);
             c->d_cst = std::max(c->d_cst, el.max_len);
         } else {
             el.off = nullptr;
@@ -522,7 +527,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     }
     for (int e = 0; e < D.n_nt; ++e) {
         const EdgeLists& el = c->nt[e];
-        D.nt[e] = NtDesc{el.from, el.to, el.off, el.adj};
+        D.nt[e] = NtDesc{el.from, el.to, el.off, el.adj, el.adj_gid};
         PosDesc& P = D.pos[el.to];
         P.nt_mask |= 1u << el.from;
         if (P.nt_first < 0) P.nt_first = e;
@@ -534,7 +539,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         bytes += 4ull * c->ncand[u];
         if (c->parent[u] >= 0) bytes += 8ull * (c->ncand[c->parent[u]] + 1) + 4ull * c->tree[u].entries;
     }
-    for (auto& el : c->nt) bytes += 8ull * (c->ncand[c->order[el.from]] + 1) + 4ull * el.entries;
+    for (auto& el : c->nt) bytes += 8ull * (c->ncand[c->order[el.from]] + 1) + 8ull * el.entries;
     c->bytes = bytes;
     HIP_TRY(hipStreamSynchronize(s));
 }

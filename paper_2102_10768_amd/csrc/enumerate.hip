@@ -41,6 +41,7 @@ struct EnumArgs {
     int32_t* rows;
     uint64_t cap;
     unsigned long long* row_cursor;
+    unsigned long long* stats;  // [images, bytes, N, M, F] or nullptr
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -82,7 +83,8 @@ __device__ void emit_rows(const EnumArgs& A, uint64_t m, bool mine, int k, int l
 }
 
 // Enumerate the image in LDS with one wavefront; returns the wavefront's count.
-__device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, const EnumArgs& A) {
+__device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, const EnumArgs& A, uint64_t& nN,
+                                    uint64_t& nM, uint64_t& nF) {
     const int lane = lane_id();
     const BlobHdr* H = (const BlobHdr*)img;
     const int k = (int)H->k;
@@ -157,11 +159,13 @@ __device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, co
         }
         const bool ok1 = valid && !(same01 && g0 == g1);
         uint64_t m1 = __ballot(ok1);
+        nN += (uint64_t)__popcll(__ballot(valid));
         if (k == 2) {
             cnt += (uint64_t)__popcll(m1);
             if (A.list) emit_rows(A, m1, ok1, 2, lane, pg, my_u, 1, g1, 0, g0);
             continue;
         }
+        nF += (uint64_t)__popcll(m1);
         while (m1) {
             const int b = __ffsll((unsigned long long)m1) - 1;
             m1 &= m1 - 1;
@@ -218,6 +222,12 @@ __device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, co
                     }
                     // Synchronizer
                     const uint64_t m = __ballot(ok);
+                    {
+                        const uint64_t nv = (uint64_t)__popcll(__ballot(val));
+                        nN += nv;
+                        nM += nv * (uint64_t)__popc(rl(my_nt, d));
+                        if (d < k - 1) nF += (uint64_t)__popcll(m);
+                    }
                     lc = setl(lc, cur + (uint32_t)CSTM_WAVE, lane, d);
                     if (d == k - 1) {
                         cnt += (uint64_t)__popcll(m);
@@ -266,85 +276,142 @@ __global__ void k_enumerate(EnumArgs A) {
             *(uint4*)(img + o) = *(const uint4*)(src + o);
         if (threadIdx.x == 0) s_next = 0;
         __syncthreads();
-        const uint64_t c = enumerate_image(img, &s_next, A);
+        uint64_t nN = 0, nM = 0, nF = 0;
+        const uint64_t c = enumerate_image(img, &s_next, A, nN, nM, nF);
         if (lane == 0 && c) atomicAdd(&A.counts[A.qids ? A.qids[b] : 0], (unsigned long long)c);
+        if (A.stats && lane == 0) {
+            if (threadIdx.x == 0) {
+                atomicAdd(&A.stats[0], 1ull);
+                atomicAdd(&A.stats[1], (unsigned long long)bytes);
+            }
+            atomicAdd(&A.stats[2], (unsigned long long)nN);
+            atomicAdd(&A.stats[3], (unsigned long long)nM);
+            atomicAdd(&A.stats[4], (unsigned long long)nF);
+        }
         __syncthreads();
     }
 }
 
 }  // namespace
 
-void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
-                        uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
+// One launch over the partition images of nq partitioned CSTs; counts go to counts_dev[slot[q]].
+void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
+                            uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
+                            cstm_enum_stats* st, hipStream_t s) {
     int64_t total = 0;
     uint64_t max_blob = 0;
-    int kq = 0;
+    for (int q = 0; q < nq; ++q) {
+        total += csts[q]->n_parts;
+        max_blob = std::max<uint64_t>(max_blob, csts[q]->max_blob);
+    }
+    if (total == 0) return;
+    CSTM_REQUIRE(total < ((int64_t)1 << 32) - 1, CSTM_EINVAL, "too many partitions for one launch");
+    DevArena mem;
+    mem.ctx = ctx;
+    unsigned long long* work = mem.get_n<unsigned long long>(6);
+    HIP_TRY(hipMemsetAsync(work, 0, 6 * sizeof(unsigned long long), s));
+    uint64_t* bl = mem.get_n<uint64_t>(total);
+    int32_t* qi = mem.get_n<int32_t>(total);
+    std::vector<int32_t> hq(total);
+    int64_t o = 0;
+    for (int q = 0; q < nq; ++q) {
+        int64_t n = csts[q]->n_parts;
+        if (!n) continue;
+        HIP_TRY(hipMemcpyAsync(bl + o, csts[q]->blob_off, n * 8, hipMemcpyDeviceToDevice, s));
+        std::fill(hq.begin() + o, hq.begin() + o + n, slot[q]);
+        o += n;
+    }
+    HIP_TRY(hipMemcpyAsync(qi, hq.data(), total * 4, hipMemcpyHostToDevice, s));
+    EnumArgs A;
+    A.blobs = bl;
+    A.qids = qi;
+    A.n_blobs = total;
+    A.head = (unsigned int*)work;
+    A.counts = counts_dev;
+    A.list = list;
+    A.rows = rows;
+    A.cap = cap;
+    A.row_cursor = row_cursor;
+    A.stats = ctx->tune.collect_stats ? work + 1 : nullptr;
+    const int waves = ctx->tune.waves_per_wg;
+    const size_t lds = (size_t)cstm_align16(max_blob);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_enumerate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ctx->lds_per_wg - 64);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    int64_t grid = (int64_t)ctx->num_cus * ctx->tune.wgs_per_cu;
+    grid = std::min<int64_t>(grid, total);
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    HIP_TRY(hipEventRecord(ev[0], s));
+    k_enumerate<<<(unsigned)grid, waves * CSTM_WAVE, lds, s>>>(A);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    float kernel_ms = 0;
+    HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    unsigned long long h[6];
+    HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st->kernel_ms += kernel_ms;
+    st->mode = CSTM_MODE_LDS;
+    st->launches += 1;
+    st->images += h[1];
+    st->image_bytes += h[2];
+    st->extensions += h[3];
+    st->edge_checks += h[4];
+    st->pushed += h[5];
+}
+
+// Enumerate nq CSTs: pick LDS images or the HBM-resident CST per the tuning,
+// run at most one launch of each kind, and return per-CST counts.
+void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
+                        uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
+    const cstm_tune& T = ctx->tune;
+    std::vector<cstm_cst*> lds_q, hbm_q;
+    std::vector<int> lds_slot, hbm_slot;
     for (int q = 0; q < nq; ++q) {
         cstm_cst* c = csts[q];
-        if (!c->partitioned) cstm_partition_run(c, 0, ctx->tune.max_list_len);
-        total += c->n_parts;
-        max_blob = std::max<uint64_t>(max_blob, c->max_blob);
-        kq = c->k;
+        if (c->empty) continue;
+        int mode = T.enum_mode;
+        if (mode == CSTM_MODE_AUTO) {
+            // partitions the caller asked for are enumerated on chip; otherwise the
+            // CST stays in HBM, where the whole GPU shares one query's search
+            mode = c->partitioned ? CSTM_MODE_LDS : CSTM_MODE_HBM;
+        }
+        if (mode == CSTM_MODE_LDS) {
+            if (!c->partitioned) cstm_partition_run(c, 0, T.max_list_len, 0);
+            lds_q.push_back(c);
+            lds_slot.push_back(q);
+        } else {
+            hbm_q.push_back(c);
+            hbm_slot.push_back(q);
+        }
     }
     DevArena mem;
     mem.ctx = ctx;
-    unsigned long long* counts = mem.get_n<unsigned long long>(nq + 2);
-    HIP_TRY(hipMemsetAsync(counts, 0, (nq + 2) * sizeof(unsigned long long), s));
-    unsigned int* head = (unsigned int*)(counts + nq);
-    unsigned long long* row_cursor = counts + nq + 1;
-    if (total > 0) {
-        CSTM_REQUIRE(total < ((int64_t)1 << 32) - 1, CSTM_EINVAL, "too many partitions for one launch");
-        const uint64_t* blobs;
-        const int32_t* qids = nullptr;
-        if (nq == 1) {
-            blobs = csts[0]->blob_off;
-        } else {
-            uint64_t* bl = mem.get_n<uint64_t>(total);
-            int32_t* qi = mem.get_n<int32_t>(total);
-            std::vector<int32_t> hq(total);
-            int64_t o = 0;
-            for (int q = 0; q < nq; ++q) {
-                int64_t n = csts[q]->n_parts;
-                if (!n) continue;
-                HIP_TRY(hipMemcpyAsync(bl + o, csts[q]->blob_off, n * 8, hipMemcpyDeviceToDevice, s));
-                std::fill(hq.begin() + o, hq.begin() + o + n, q);
-                o += n;
-            }
-            HIP_TRY(hipMemcpyAsync(qi, hq.data(), total * 4, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            blobs = bl;
-            qids = qi;
-        }
-        EnumArgs A;
-        A.blobs = blobs;
-        A.qids = qids;
-        A.n_blobs = total;
-        A.head = head;
-        A.counts = counts;
-        A.list = list;
-        A.rows = rows;
-        A.cap = cap;
-        A.row_cursor = row_cursor;
-        const int waves = ctx->tune.waves_per_wg;
-        const size_t lds = (size_t)cstm_align16(max_blob);
-        static bool attr_set = false;
-        if (!attr_set) {
-            (void)hipFuncSetAttribute((const void*)k_enumerate, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)ctx->lds_per_wg - 64);
-            (void)hipGetLastError();
-            attr_set = true;
-        }
-        int64_t grid = (int64_t)ctx->num_cus * ctx->tune.wgs_per_cu;
-        grid = std::min<int64_t>(grid, total);
-        k_enumerate<<<(unsigned)grid, waves * CSTM_WAVE, lds, s>>>(A);
-        HIP_TRY(hipGetLastError());
-    }
-    std::vector<unsigned long long> h(nq + 2);
-    HIP_TRY(hipMemcpyAsync(h.data(), counts, (nq + 2) * 8, hipMemcpyDeviceToHost, s));
+    unsigned long long* counts = mem.get_n<unsigned long long>(nq + 1);
+    HIP_TRY(hipMemsetAsync(counts, 0, (nq + 1) * sizeof(unsigned long long), s));
+    unsigned long long* row_cursor = counts + nq;
+    cstm_enum_stats st{};
+    if (!lds_q.empty())
+        cstm_enumerate_lds_run(ctx, (int)lds_q.size(), lds_q.data(), lds_slot.data(), list, rows, cap, counts,
+                               row_cursor, &st, s);
+    if (!hbm_q.empty())
+        cstm_enumerate_global_run(ctx, (int)hbm_q.size(), hbm_q.data(), hbm_slot.data(), list, rows, cap, counts,
+                                  row_cursor, &st, s);
+    std::vector<unsigned long long> h(nq + 1);
+    HIP_TRY(hipMemcpyAsync(h.data(), counts, (nq + 1) * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    ctx->last_enum = st;
     for (int q = 0; q < nq; ++q) counts_host[q] = h[q];
-    if (rows_written) *rows_written = std::min<uint64_t>(h[nq + 1], cap);
-    (void)kq;
+    if (rows_written) *rows_written = std::min<uint64_t>(h[nq], cap);
 }
 
 extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap, uint64_t* count_out,

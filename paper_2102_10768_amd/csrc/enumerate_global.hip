@@ -1,0 +1,517 @@
+// enumerate_global.hip -- enumeration with the CST resident in HBM (L2/MALL) and
+// GPU-wide dynamic load balancing.
+//
+// This is the "CST read from device memory" variant of the paper's matcher
+// (FAST-DRAM in Section VII-A), rebuilt for a GPU: the CST of one query is a
+// few hundred KB to a few MB, so it stays in each XCD's L2 / the Infinity
+// Cache, and every wavefront can work on any part of it.  That removes the
+// replication that partitioning into 160 KB LDS images causes on power-law
+// graphs, and lets the whole GPU share one query's search.
+//
+// Work unit: a task = (query slot, level j, a range of the candidate list at
+// level j, the mapped candidates of levels 0..j-1).  Wavefronts pop tasks from
+// a ring buffer and run the same bounded depth-first expansion as the on-chip
+// enumerator (64 candidates per level and round, ballot compaction, deepest
+// level first).  When some wavefronts are idle, a busy wavefront donates the
+// unexpanded remainder of its shallowest open level as a new task, so a skewed
+// search (one hub candidate owning most embeddings) spreads over the machine.
+// Edge validation reads the non-tree candidate list of the mapped neighbour,
+// stored as ascending data-vertex ids, by binary search.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+struct GTask {
+    int32_t q;
+    int32_t depth;
+    int64_t lo, hi;  // depth 0: root candidate indices; else offsets into the level's tree list array
+    int32_t prefix[CSTM_MAX_K];
+};
+
+// Each counter sits on its own 256-byte line: thousands of wavefronts poll
+// them, and sharing a line would serialise every poll behind every update.
+struct alignas(256) GLine {
+    unsigned long long v;
+    unsigned long long pad[31];
+};
+struct GQueue {
+    GLine head;         // next ticket a consumer takes (may run ahead of tail: waiting consumers)
+    GLine tail;         // next ticket a producer fills
+    GLine outstanding;  // tasks pushed and not finished
+    GLine abort;        // 1: give up (idle limit), 2: deadline passed
+};
+
+struct GArgs {
+    const CstDev* descs;  // nq descriptors, contiguous
+    const int32_t* slot;  // count slot of each descriptor
+    int nq;
+    GQueue* qu;
+    GTask* tasks;
+    unsigned int* ready;
+    unsigned long long qmask;
+    int qlog;
+    unsigned long long margin;
+    unsigned long long* counts;
+    int list;
+    int32_t* rows;
+    uint64_t cap;
+    unsigned long long* row_cursor;
+    unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks] or nullptr
+    uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave may wait
+    uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
+    int donate_period;          // chunks between donation checks (<= 0: never)
+};
+
+__device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
+
+__device__ inline int mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ inline int32_t rl(int32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ inline uint32_t rl(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+__device__ inline int64_t rl(int64_t x, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline uint64_t rl(uint64_t x, int l) { return (uint64_t)rl((int64_t)x, l); }
+__device__ inline const void* rlp(const void* p, int l) { return (const void*)rl((uint64_t)(uintptr_t)p, l); }
+
+template <class T>
+__device__ inline T setl(T cur, T val, int lane, int l) {
+    return lane == l ? val : cur;
+}
+
+template <class T>
+__device__ inline T ld_acq(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T ld_rlx(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Binary search of x in the ascending array a[lo, hi).
+__device__ inline bool contains(const int32_t* a, int64_t lo, int64_t hi, int32_t x) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t y = a[mid];
+        if (y == x) return true;
+        if (y < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return false;
+}
+
+// Push a task built from the wave's registers: levels 0..depth-1 from pl.
+// Returns false (nothing pushed) when the ring is close to full.
+__device__ bool push_task(const GArgs& A, int q, int depth, int64_t lo, int64_t hi, int32_t pl, int lane) {
+    unsigned long long t = 0;
+    bool ok = true;
+    if (lane == 0) {
+        const long long pending = (long long)(ld_rlx(&A.qu->tail.v) - ld_rlx(&A.qu->head.v));
+        if (pending + (long long)A.margin > (long long)A.qmask) {
+            ok = false;
+        } else {
+            atomicAdd(&A.qu->outstanding.v, 1ull);
+            t = atomicAdd(&A.qu->tail.v, 1ull);
+        }
+    }
+    ok = __shfl(ok ? 1 : 0, 0) != 0;
+    if (!ok) return false;
+    t = __shfl(t, 0);
+    GTask* T = &A.tasks[t & A.qmask];
+    if (lane < CSTM_MAX_K) T->prefix[lane] = lane < depth ? pl : 0;
+    if (lane == 0) {
+        T->q = q;
+        T->depth = depth;
+        T->lo = lo;
+        T->hi = hi;
+    }
+    __threadfence();
+    if (lane == 0)
+        __hip_atomic_store(&A.ready[t & A.qmask], (unsigned int)((t >> A.qlog) + 1), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// Take the next ticket and wait for its task.  Each waiting wavefront polls
+// only its own slot, so an idle machine does not hammer one cache line.
+// Returns the slot, -1 when all work is done, -2 on abort (limit or deadline).
+__device__ long long pop_task(const GArgs& A, int lane) {
+    long long slot = -1;
+    if (lane == 0) {
+        const unsigned long long h = atomicAdd(&A.qu->head.v, 1ull);
+        const unsigned int lap = (unsigned int)((h >> A.qlog) + 1);
+        unsigned int* rp = &A.ready[h & A.qmask];
+        const uint64_t t0 = now_ticks();
+        int polls = 0, nap = 1;
+        for (;;) {
+            // relaxed polls leave the CU's L1 alone; one acquire fence once the task is there
+            if (ld_rlx(rp) == lap) {
+                __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                slot = (long long)(h & A.qmask);
+                break;
+            }
+            if (++polls >= 16) {
+                polls = 0;
+                if (ld_rlx(&A.qu->outstanding.v) == 0) {
+                    slot = -1;
+                    break;
+                }
+                if (ld_rlx(&A.qu->abort.v)) {
+                    slot = -2;
+                    break;
+                }
+                const uint64_t now = now_ticks();
+                if (A.deadline && now > A.deadline) {
+                    atomicExch(&A.qu->abort.v, 2ull);
+                    slot = -2;
+                    break;
+                }
+                if (now - t0 > A.idle_limit) {
+                    atomicExch(&A.qu->abort.v, 1ull);
+                    slot = -2;
+                    break;
+                }
+            }
+            for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(16);
+            nap = nap < 16 ? nap + 1 : 16;
+        }
+    }
+    return __shfl(slot, 0);
+}
+
+__global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
+    const int lane = lane_id();
+    if (A.deadline) A.deadline += now_ticks();  // relative on entry, absolute from here on
+    // per-query position records, held one per lane (lane d = position d)
+    int cur_q = -1, k = 0;
+    const int32_t* my_gid = nullptr;
+    const int64_t* my_toff = nullptr;
+    const int32_t* my_tadj = nullptr;
+    int32_t my_par = -1;
+    uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0;
+    const CstDev* D = nullptr;
+    uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, ntasks = 0, ndon = 0;
+    uint64_t t_wait = 0, t_busy = 0;
+    for (;;) {
+        const uint64_t w0 = now_ticks();
+        const long long slot = pop_task(A, lane);
+        const uint64_t w1 = now_ticks();
+        t_wait += w1 - w0;
+        if (slot < 0) break;
+        const GTask* T = &A.tasks[slot];
+        const int q = T->q;
+        const int j = T->depth;
+        int64_t lo = T->lo, hi = T->hi;
+        int32_t pre = lane < CSTM_MAX_K ? T->prefix[lane] : 0;
+        ++ntasks;
+        if (q != cur_q) {
+            if (cur_q >= 0 && cnt) {
+                if (lane == 0) atomicAdd(&A.counts[A.slot[cur_q]], (unsigned long long)cnt);
+                cnt = 0;
+            }
+            cur_q = q;
+            D = &A.descs[q];
+            k = D->k;
+            if (lane < k) {
+                const PosDesc& P = D->pos[lane];
+                my_gid = P.gid;
+                my_toff = P.toff;
+                my_tadj = P.tadj;
+                my_par = P.par;
+                my_same = P.same_mask;
+                my_nt = P.nt_mask;
+                my_ntf = (uint32_t)(P.nt_first < 0 ? 0 : P.nt_first);
+                my_u = (uint32_t)P.u;
+            }
+        }
+        // level registers: lane d holds level d
+        int32_t pl = lane < j ? pre : 0;
+        int32_t pg = 0;
+        if (lane < j) pg = my_gid[pl];
+        int64_t lc = 0, le = 0;
+        uint64_t lm = 0;
+        lc = setl(lc, lo, lane, j);
+        le = setl(le, hi, lane, j);
+        int d = j;
+        uint32_t since_check = 0;
+        for (;;) {
+            uint64_t M = rl(lm, d);
+            const int64_t cur = rl(lc, d);
+            if (M == 0) {
+                const int64_t end = rl(le, d);
+                if (cur >= end) {
+                    if (d == j) break;
+                    --d;
+                    continue;
+                }
+                const int64_t idx = cur + lane;
+                const bool val = idx < end;
+                const int32_t* gid = (const int32_t*)rlp(my_gid, d);
+                int32_t v = 0;
+                if (val) v = d == 0 ? (int32_t)idx : ((const int32_t*)rlp(my_tadj, d))[idx];
+                const int32_t g = val ? gid[v] : -1;
+                bool ok = val;
+                uint32_t same = rl(my_same, d);
+                while (same) {
+                    const int jj = __ffs(same) - 1;
+                    same &= same - 1;
+                    ok = ok && g != rl(pg, jj);
+                }
+                uint32_t ntm = rl(my_nt, d);
+                uint32_t e = rl(my_ntf, d);
+                const uint32_t n_nt_here = (uint32_t)__popc(ntm);
+                while (ntm) {
+                    const int jj = __ffs(ntm) - 1;
+                    ntm &= ntm - 1;
+                    const NtDesc& N = D->nt[e++];
+                    const int32_t x = rl(pl, jj);
+                    if (ok) ok = contains(N.adj_gid, N.off[x], N.off[x + 1], g);
+                }
+                const uint64_t m = __ballot(ok);
+                {
+                    const uint64_t nv = (uint64_t)__popcll(__ballot(val));
+                    nN += nv;
+                    nM += nv * n_nt_here;
+                }
+                lc = setl(lc, cur + (int64_t)CSTM_WAVE, lane, d);
+                if (d == k - 1) {
+                    cnt += (uint64_t)__popcll(m);
+                    if (A.list && m) {
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m));
+                        base = __shfl(base, 0);
+                        if (ok) {
+                            const uint64_t r = base + (uint64_t)mbcnt(m);
+                            if (r < A.cap) {
+                                int32_t* row = A.rows + r * (uint64_t)k;
+                                for (int i = 0; i < k; ++i) row[rl(my_u, i)] = i == d ? g : rl(pg, i);
+                            }
+                        }
+                    }
+                } else if (m) {
+                    M = m;
+                    nF += (uint64_t)__popcll(m);
+                }
+                // every few chunks: stop on abort or deadline; donate the untouched
+                // remainder of the shallowest open level when a consumer is waiting
+                if (++since_check >= (uint32_t)(A.donate_period > 0 ? A.donate_period : 64)) {
+                    since_check = 0;
+                    int want = 0;
+                    if (lane == 0) {
+                        if (ld_rlx(&A.qu->abort.v)) want = -1;
+                        else if (A.deadline && now_ticks() > A.deadline) {
+                            atomicExch(&A.qu->abort.v, 2ull);
+                            want = -1;
+                        } else if (A.donate_period > 0) {
+                            const unsigned long long t2 = ld_rlx(&A.qu->tail.v), h2 = ld_rlx(&A.qu->head.v);
+                            want = (long long)(h2 - t2) > 0 ? 1 : 0;
+                        }
+                    }
+                    want = __shfl(want, 0);
+                    if (want < 0) break;
+                    if (want) {
+                        // shallowest open level first: its untouched list remainder, or
+                        // (above the current level) the survivors not yet descended into,
+                        // given away as a range the receiver re-checks
+                        for (int dd = j; dd <= d && dd < k - 1; ++dd) {
+                            const int64_t c2 = rl(lc, dd), e2 = rl(le, dd);
+                            if (c2 < e2) {
+                                if (push_task(A, q, dd, c2, e2, pl, lane)) {
+                                    le = setl(le, c2, lane, dd);
+                                    ++ndon;
+                                }
+                                break;
+                            }
+                            const uint64_t Mr = dd < d ? rl(lm, dd) : 0;
+                            if (Mr) {
+                                const int64_t cs = c2 - (int64_t)CSTM_WAVE;
+                                const int64_t from = cs + (int64_t)(__ffsll((unsigned long long)Mr) - 1);
+                                const int64_t to = c2 < e2 ? c2 : e2;
+                                if (from < to && push_task(A, q, dd, from, to, pl, lane)) {
+                                    lm = setl(lm, (uint64_t)0, lane, dd);
+                                    ++ndon;
+                                }
+                                break;
+                            }
+                        }
+                    }
+                }
+                if (M == 0) continue;
+            }
+            // descend into the lowest survivor of the current chunk at level d
+            const int b = __ffsll((unsigned long long)M) - 1;
+            M &= M - 1;
+            lm = setl(lm, M, lane, d);
+            const int64_t chunk = rl(lc, d) - (int64_t)CSTM_WAVE;
+            const int32_t v =
+                d == 0 ? (int32_t)(chunk + b) : ((const int32_t*)rlp(my_tadj, d))[chunk + b];
+            const int32_t g = ((const int32_t*)rlp(my_gid, d))[v];
+            pl = setl(pl, v, lane, d);
+            pg = setl(pg, g, lane, d);
+            ++d;
+            const int p = rl(my_par, d);
+            const int64_t* toff = (const int64_t*)rlp(my_toff, d);
+            const int32_t x = rl(pl, p);
+            lc = setl(lc, toff[x], lane, d);
+            le = setl(le, toff[x + 1], lane, d);
+            lm = setl(lm, (uint64_t)0, lane, d);
+        }
+        if (lane == 0) atomicAdd(&A.qu->outstanding.v, ~0ull);
+        t_busy += now_ticks() - w1;
+    }
+    if (cur_q >= 0 && cnt && lane == 0) atomicAdd(&A.counts[A.slot[cur_q]], (unsigned long long)cnt);
+    if (A.stats && lane == 0) {
+        atomicAdd(&A.stats[0], (unsigned long long)ntasks);
+        atomicAdd(&A.stats[1], (unsigned long long)ndon);
+        atomicAdd(&A.stats[2], (unsigned long long)nN);
+        atomicAdd(&A.stats[3], (unsigned long long)nM);
+        atomicAdd(&A.stats[4], (unsigned long long)nF);
+        atomicAdd(&A.stats[5], (unsigned long long)t_wait);
+        atomicAdd(&A.stats[6], (unsigned long long)t_busy);
+    }
+}
+
+// Initial tasks: runs of root candidates of every query.
+__global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t* __restrict__ nroot,
+                       const int64_t* __restrict__ chunk, int nq, unsigned long long total) {
+    unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        int q = 0;
+        while (q + 1 < nq && (long long)t >= first[q + 1]) ++q;
+        const int64_t i = (int64_t)t - first[q];
+        GTask& T = A.tasks[t & A.qmask];
+        T.q = q;
+        T.depth = 0;
+        T.lo = i * chunk[q];
+        T.hi = T.lo + chunk[q] < nroot[q] ? T.lo + chunk[q] : nroot[q];
+        for (int p = 0; p < CSTM_MAX_K; ++p) T.prefix[p] = 0;
+        A.ready[t & A.qmask] = (unsigned int)((t >> A.qlog) + 1);
+    }
+}
+
+}  // namespace
+
+// Count (or list) the embeddings of nq CSTs in one launch, the CSTs read from
+// HBM; counts go to counts_dev[slot[q]].
+void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
+                               uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
+                               cstm_enum_stats* st, hipStream_t s) {
+    const int qlog = 20;
+    const unsigned long long qcap = 1ull << qlog;
+    std::vector<int64_t> first(nq + 1, 0), nroot(nq, 0), chunk(nq, 1);
+    for (int q = 0; q < nq; ++q) {
+        const cstm_cst* c = csts[q];
+        nroot[q] = c->empty ? 0 : c->host_desc.pos[0].n;
+        // one root candidate per task unless the batch would fill half the ring
+        int64_t per = std::max<int64_t>(1, (nroot[q] * 2 * std::max(1, nq) + (int64_t)qcap - 1) / (int64_t)qcap);
+        chunk[q] = per;
+        first[q + 1] = first[q] + (nroot[q] + per - 1) / per;
+    }
+    const unsigned long long total = (unsigned long long)first[nq];
+    CSTM_REQUIRE(total < qcap / 2, CSTM_EINVAL, "too many root candidates for the task ring");
+    if (total == 0) return;
+    // workspace kept by the context: ring, ready flags, queue state, counters, descriptors
+    // workspace kept by the context, every region 256-byte aligned and sized by sizeof():
+    // ring | ready flags | queue state | work counters | descriptors | seed tables | count slots
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t off_ready = up(qcap * sizeof(GTask));
+    const size_t off_qu = up(off_ready + qcap * sizeof(unsigned int));
+    const size_t off_work = up(off_qu + sizeof(GQueue));
+    const size_t off_desc = up(off_work + 8 * sizeof(unsigned long long));
+    const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
+    const size_t off_slot = up(off_meta + (3 * (size_t)nq + 1) * sizeof(int64_t));
+    const size_t need = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t ready_b = qcap * sizeof(unsigned int);
+    if (ctx->enum_ws_bytes < need) {
+        HIP_TRY(hipStreamSynchronize(s));
+        ctx->dfree(ctx->enum_ws);
+        ctx->enum_ws = nullptr;
+        ctx->enum_ws_bytes = 0;
+        size_t want = need + need / 4;
+        ctx->enum_ws = ctx->dmalloc(want);
+        ctx->enum_ws_bytes = want;
+    }
+    uint8_t* ws = (uint8_t*)ctx->enum_ws;
+    GTask* tasks = (GTask*)ws;
+    unsigned int* ready = (unsigned int*)(ws + off_ready);
+    GQueue* qu = (GQueue*)(ws + off_qu);
+    unsigned long long* work = (unsigned long long*)(ws + off_work);
+    CstDev* descs = (CstDev*)(ws + off_desc);
+    int64_t* meta = (int64_t*)(ws + off_meta);
+    int32_t* dslot = (int32_t*)(ws + off_slot);
+    for (int q = 0; q < nq; ++q)
+        HIP_TRY(hipMemcpyAsync(descs + q, &csts[q]->host_desc, sizeof(CstDev), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ready, 0, ready_b, s));
+    HIP_TRY(hipMemsetAsync(work, 0, 8 * sizeof(unsigned long long), s));
+    GQueue init;
+    std::memset(&init, 0, sizeof(init));
+    init.tail.v = total;
+    init.outstanding.v = total;
+    HIP_TRY(hipMemcpyAsync(qu, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta, first.data(), (nq + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta + nq + 1, nroot.data(), nq * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta + 2 * nq + 1, chunk.data(), nq * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dslot, slot, nq * 4, hipMemcpyHostToDevice, s));
+    GArgs A;
+    A.descs = descs;
+    A.slot = dslot;
+    A.nq = nq;
+    A.qu = qu;
+    A.tasks = tasks;
+    A.ready = ready;
+    A.qmask = qcap - 1;
+    A.qlog = qlog;
+    A.margin = 1ull << 15;
+    A.counts = counts_dev;
+    A.list = list;
+    A.rows = rows;
+    A.cap = cap;
+    A.row_cursor = row_cursor;
+    A.stats = ctx->tune.collect_stats ? work : nullptr;
+    A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
+    A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
+    A.donate_period = ctx->tune.hbm_donate_period;
+    k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, nq,
+                                                                  total);
+    HIP_TRY(hipGetLastError());
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    HIP_TRY(hipEventRecord(ev[0], s));
+    const unsigned grid = (unsigned)(ctx->num_cus * ctx->tune.hbm_wgs_per_cu);
+    k_enumerate_global<<<grid, 256, 0, s>>>(A);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    float kernel_ms = 0;
+    HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    unsigned long long h[7];
+    GQueue fin{};
+    HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&fin, qu, sizeof(fin), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st->kernel_ms += kernel_ms;
+    st->mode = CSTM_MODE_HBM;
+    st->launches += 1;
+    st->images += h[0];
+    st->image_bytes += h[1];
+    st->extensions += h[2];
+    st->edge_checks += h[3];
+    st->pushed += h[4];
+    st->busy_frac = (h[5] + h[6]) ? (double)h[6] / (double)(h[5] + h[6]) : 0.0;
+    ctx->last_enum = *st;  // kept even when the launch is reported as failed below
+    CSTM_REQUIRE(fin.abort.v != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
+    CSTM_REQUIRE(!fin.abort.v && fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
+}

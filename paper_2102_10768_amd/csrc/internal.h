@@ -60,6 +60,10 @@ struct cstm_ctx {
     cstm_tune tune{};
     int num_cus = 0;
     int64_t lds_per_wg = 0;
+    cstm_enum_stats last_enum{};
+    // enumeration workspace reused across launches
+    void* enum_ws = nullptr;
+    size_t enum_ws_bytes = 0;
     // reusable temporary storage for library scans and sorts
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
@@ -134,6 +138,7 @@ struct NtDesc {
     int32_t a, b;
     const int64_t* off;
     const int32_t* adj;
+    const int32_t* adj_gid;  // entries as data-vertex ids, ascending within each list
 };
 
 #define CSTM_MAX_NT (CSTM_MAX_K * (CSTM_MAX_K - 1) / 2)
@@ -201,7 +206,8 @@ struct Spec {
 struct EdgeLists {
     int32_t from = -1, to = -1;  // positions
     int64_t* off = nullptr;      // device, n_from + 1
-    int32_t* adj = nullptr;      // device
+    int32_t* adj = nullptr;      // device: indices into the later candidate set
+    int32_t* adj_gid = nullptr;  // device, non-tree lists only: the same entries as data-vertex ids (ascending)
     int64_t entries = 0;
     int32_t max_len = 0;
 };
@@ -258,6 +264,13 @@ inline unsigned cstm_blocks(int64_t items, int per_block, unsigned cap = 1u << 2
     return (unsigned)b;
 }
 
-void cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list);
+// Returns false (and leaves the CST unpartitioned) if the images would exceed max_total_bytes (0 = no limit).
+bool cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list, uint64_t max_total_bytes = 0);
+void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
+                            uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
+                            cstm_enum_stats* st, hipStream_t s);
+void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
+                               uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
+                               cstm_enum_stats* st, hipStream_t s);
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
                         uint64_t* counts_host, uint64_t* rows_written, hipStream_t s);

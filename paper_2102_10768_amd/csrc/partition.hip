@@ -468,7 +468,7 @@ static uint64_t min_image_bytes(const cstm_cst* c) {
     return cstm_align16(b);
 }
 
-void cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list) {
+bool cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list, uint64_t max_total_bytes) {
     cstm_ctx* ctx = c->ctx;
     hipStream_t s = c->stream;
     if (budget == 0) budget = ctx->tune.part_budget_bytes;
@@ -489,7 +489,7 @@ void cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list) {
     c->part_budget = budget;
     c->part_max_list = max_list;
     c->partitioned = true;
-    if (c->empty) return;
+    if (c->empty) return true;
 
     const int k = c->k;
     const CstDev& D = c->host_desc;
@@ -610,6 +610,18 @@ void cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list) {
         std::swap(spec_a, spec_b);
         n_in = (int64_t)after.n_out;
         if (n_in > spec_cap) n_in = spec_cap;
+        if (max_total_bytes &&
+            (after.arena_used > max_total_bytes || (uint64_t)n_in * 4096ull > max_total_bytes * 64ull)) {
+            // the images replicate the CST beyond the caller's limit: give up
+            c->mem.release(arena);
+            c->mem.release(blob_off);
+            c->mem.release(spec_a);
+            c->mem.release(spec_b);
+            c->mem.release(scratch);
+            c->mem.release(dc);
+            c->partitioned = false;
+            return false;
+        }
     }
     Counters fin;
     HIP_TRY(hipMemcpyAsync(&fin, dc, sizeof(fin), hipMemcpyDeviceToHost, s));
@@ -632,6 +644,7 @@ void cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list) {
     c->mem.release(spec_b);
     c->mem.release(scratch);
     c->mem.release(dc);
+    return true;
 }
 
 extern "C" cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max_list_len,

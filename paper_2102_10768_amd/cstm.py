@@ -33,7 +33,30 @@ class cstm_tune(ctypes.Structure):
         ("max_list_len", ctypes.c_int32),
         ("waves_per_wg", ctypes.c_int32),
         ("wgs_per_cu", ctypes.c_int32),
+        ("collect_stats", ctypes.c_int32),
+        ("enum_mode", ctypes.c_int32),
+        ("max_replication", ctypes.c_int32),
+        ("deadline_ms", ctypes.c_int32),
+        ("hbm_wgs_per_cu", ctypes.c_int32),
+        ("hbm_donate_period", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+    ]
+
+
+MODE_AUTO, MODE_LDS, MODE_HBM = 0, 1, 2
+
+
+class cstm_enum_stats(ctypes.Structure):
+    _fields_ = [
+        ("kernel_ms", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("launches", ctypes.c_int32),
+        ("images", ctypes.c_uint64),
+        ("image_bytes", ctypes.c_uint64),
+        ("extensions", ctypes.c_uint64),
+        ("edge_checks", ctypes.c_uint64),
+        ("pushed", ctypes.c_uint64),
+        ("busy_frac", ctypes.c_double),
     ]
 
 
@@ -63,7 +86,7 @@ EXPORTS = [
     "cstm_graph_load", "cstm_graph_free", "cstm_graph_info",
     "cstm_cst_build", "cstm_cst_partition", "cstm_cst_info_get", "cstm_cst_candidates",
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
-    "cstm_last_error", "cstm_version",
+    "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats",
 ]
 
 _lib = None
@@ -103,6 +126,7 @@ def load_library():
         "cstm_cst_times": (st, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
         "cstm_cst_free": (None, [P]),
+        "cstm_ctx_last_enum_stats": (st, [P, ctypes.POINTER(cstm_enum_stats)]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -173,6 +197,11 @@ class Context:
         cur.update(values)
         t = cstm_tune(**cur)
         _check(load_library().cstm_ctx_set_tune(self.handle, ctypes.byref(t)))
+
+    def last_enum_stats(self) -> dict:
+        v = cstm_enum_stats()
+        _check(load_library().cstm_ctx_last_enum_stats(self.handle, ctypes.byref(v)))
+        return {f: getattr(v, f) for f, _ in cstm_enum_stats._fields_}
 
     def lds_bytes(self) -> int:
         v = ctypes.c_int64()

@@ -1,0 +1,37 @@
+"""Named synthetic workloads (graph recipe + query recipe), shaped like the paper's.
+
+The paper measures on LDBC-SNB social graphs (Section VII, Table III) with
+queries from LDBC tasks; neither is available, so these seeded synthetic
+stand-ins take their place.  Only recipes live here; which drawn queries make
+up a screened set, and their expected counts, are written by
+``tests/golden/make_workloads.py`` (from the CPU oracle) into
+``tests/golden/<name>.json``.
+"""
+
+from __future__ import annotations
+
+SMALL = {
+    "name": "c1",
+    "title": "ER G(3000, 10/2999), 20 uniform labels, 8 random-walk queries of 4 vertices",
+    "graph": {"kind": "er", "n": 3000, "p": 10 / 2999, "seed": 11, "labels": {"kind": "uniform", "L": 20}},
+    "queries": {"sizes": [4] * 8, "seed": 21},
+}
+
+POWER_LAW_1M = {
+    "name": "c2",
+    "title": "Chung-Lu 1M vertices, ~16M edges, gamma 2.3, 32 Zipf(1.0) labels; 100 screened 8-vertex queries",
+    "graph": {"kind": "chung_lu", "n": 1_000_000, "m": 16_000_000, "gamma": 2.3, "seed": 12,
+              "labels": {"kind": "zipf", "L": 32, "s": 1.0}},
+    # 50 sparse (average query degree < 3) and 50 dense (>= 3) random-walk queries
+    "queries": {"k": 8, "sparse": 50, "dense": 50, "seed": 22},
+}
+
+RMAT_22 = {
+    "name": "c3",
+    "title": "R-MAT scale 22 (a,b,c = .57,.19,.19), 64 uniform labels; 1000 screened queries of 4..16 vertices",
+    "graph": {"kind": "rmat", "scale": 22, "edge_factor": 16, "a": 0.57, "b": 0.19, "c": 0.19, "seed": 13,
+              "labels": {"kind": "uniform", "L": 64}},
+    "queries": {"k_min": 4, "k_max": 16, "count": 1000, "seed": 23},
+}
+
+ALL = {w["name"]: w for w in (SMALL, POWER_LAW_1M, RMAT_22)}

@@ -236,3 +236,95 @@ def relabel_query(q: Query, perm) -> Query:
     lab[perm] = q.qlabel
     e = [(int(min(perm[a], perm[b])), int(max(perm[a], perm[b]))) for a, b in np.asarray(q.qedges).reshape(-1, 2)]
     return query(lab, e)
+
+
+class LabelBlocks:
+    """Adjacency of G cut into label-by-label blocks, for fast labelled tree DPs.
+
+    Block (a, b) holds the edges from label-a vertices to label-b vertices, so a
+    product that only needs label-b values on label-a rows touches only those
+    edges.
+    """
+
+    def __init__(self, g: Graph, dtype=np.float64):
+        self.g = g
+        L = int(g.label.max()) + 1 if g.n else 0
+        self.L = L
+        self.members = [np.flatnonzero(g.label == l) for l in range(L)]
+        self.index = np.zeros(g.n, dtype=np.int64)
+        for l in range(L):
+            self.index[self.members[l]] = np.arange(self.members[l].shape[0])
+        self.dtype = dtype
+        A = adjacency(g, dtype=dtype).tocsr()
+        self.rows = [A[self.members[l], :] for l in range(L)]
+        self.blocks = {}
+        self.deg = np.diff(g.row_ptr)
+
+    def block(self, a: int, b: int):
+        key = (a, b)
+        if key not in self.blocks:
+            self.blocks[key] = self.rows[a][:, self.members[b]].tocsr()
+        return self.blocks[key]
+
+    def tree_bound(self, q: Query, degree_filter: bool = True) -> float:
+        """Labelled spanning-tree homomorphism count (float64): an upper bound on the embedding count."""
+        k = q.k
+        adj = [[] for _ in range(k)]
+        for a, b in np.asarray(q.qedges).reshape(-1, 2):
+            adj[int(a)].append(int(b))
+            adj[int(b)].append(int(a))
+        parent = [-1] * k
+        order = [0]
+        seen = {0}
+        for u in order:
+            for w in sorted(adj[u]):
+                if w not in seen:
+                    seen.add(w)
+                    parent[w] = u
+                    order.append(w)
+        f = [None] * k
+        for u in reversed(order):
+            lu = int(q.qlabel[u])
+            if lu >= self.L:
+                return 0.0
+            x = np.ones(self.members[lu].shape[0], dtype=self.dtype)
+            if degree_filter:
+                x *= (self.deg[self.members[lu]] >= len(adj[u])).astype(self.dtype)
+            for c in range(k):
+                if parent[c] == u:
+                    x = x * (self.block(lu, int(q.qlabel[c])) @ f[c])
+            f[u] = x
+        if self.dtype == np.int64:
+            return int(f[0].sum())
+        return float(f[0].sum())
+
+
+def is_tree_with_distinct_labels(q: Query) -> bool:
+    return q.m_q == q.k - 1 and len(set(int(x) for x in q.qlabel)) == q.k
+
+
+class ExactTreeCounter(LabelBlocks):
+    """Exact embedding counts of tree queries with pairwise-distinct labels, at any graph size.
+
+    For such a query an injective map is automatic, so the embeddings are the
+    label-preserving homomorphisms of the tree: the DP of
+    :func:`tree_homomorphism_count`, run on label blocks in int64 (checked to fit).
+    """
+
+    def __init__(self, g: Graph):
+        super().__init__(g, dtype=np.int64)
+        self.frows = [r.astype(np.float64) for r in self.rows]
+        self.fblocks = {}
+
+    def count(self, q: Query) -> int:
+        if not is_tree_with_distinct_labels(q):
+            raise ValueError("not a tree with pairwise-distinct labels")
+        # a float64 pass first proves every intermediate fits in int64
+        fl = LabelBlocks.__new__(LabelBlocks)
+        fl.__dict__.update(self.__dict__)
+        fl.dtype = np.float64
+        fl.blocks = self.fblocks
+        fl.rows = self.frows
+        if fl.tree_bound(q, degree_filter=False) >= 2.0**60:
+            raise OverflowError("count does not fit in int64")
+        return int(self.tree_bound(q, degree_filter=False))

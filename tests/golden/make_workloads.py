@@ -1,0 +1,153 @@
+"""Write the screened query sets and their expected counts for the named workloads.
+
+    python tests/golden/make_workloads.py c1
+    python tests/golden/make_workloads.py c2 [--budget 200000000] [--count-cap 20000000000]
+
+Expected values come from the CPU oracle (``oracle``); inputs come only
+from ``synth``.  For the sparse class of c2 the expected count is the exact
+labelled tree DP of ``closed_forms`` (see below).
+
+Screen (deterministic, host-independent): walks are drawn in order from the
+seeded query stream and join their class (sparse: average query degree below
+3, dense: 3 or more) while it has room.
+  sparse: the query must be a tree with pairwise-distinct labels and have at
+          most count_cap embeddings; its exact count is the labelled tree
+          homomorphism DP (injectivity is automatic for such queries), a pin
+          independent of the oracle that is exact at any graph size;
+  dense:  the oracle must finish it within node_budget visited partial
+          embeddings (at most dense_tries attempts).
+On the power-law graph almost every random-walk query has 10^9 to 10^25
+embeddings; the screen keeps the ones an exact reference can still count.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import closed_forms as cf  # noqa: E402
+from synth import make_graph, query_set  # noqa: E402
+from synth.graphs import _rng  # noqa: E402
+from synth.queries import STREAM_QUERIES, random_walk_query  # noqa: E402
+from synth.workloads import ALL  # noqa: E402
+
+
+def write(name: str, payload: dict):
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(payload, f, indent=1)
+    os.replace(path + ".tmp", path)
+    print(f"wrote {path}", flush=True)
+
+
+def make_small(w: dict):
+    g = make_graph(w["graph"])
+    qs = query_set(g, w["queries"]["sizes"], w["queries"]["seed"])
+    out = []
+    for q in qs:
+        r = oracle.match(g, q, list_rows=True, cap=1 << 20)
+        assert r.status == oracle.OK
+        d = q.to_dict()
+        d.update(count=r.count, nodes=r.nodes)
+        out.append(d)
+    write(w["name"], {"workload": w, "graph_summary": g.summary(), "oracle": {"threads": r.threads},
+                      "queries": out})
+
+
+def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap: int, dense_tries: int):
+    """Screen random walks into the sparse and dense classes (see the module docstring)."""
+    g = make_graph(w["graph"])
+    print("graph", g.summary(), flush=True)
+    exact = cf.ExactTreeCounter(g)
+    spec = w["queries"]
+    quota = {"sparse": int(spec["sparse"]), "dense": int(spec["dense"])}
+    got = {"sparse": [], "dense": []}
+    rng = _rng(spec["seed"], STREAM_QUERIES)
+    stats = {"draws": 0, "skipped_full": 0, "sparse_not_distinct_label_tree": 0, "sparse_over_cap": 0,
+             "dense_tried": 0, "dense_over_budget": 0, "dense_not_tried": 0}
+    t_start = time.time()
+    for draw in range(max_draws):
+        if all(len(got[c]) >= quota[c] for c in quota):
+            break
+        q = random_walk_query(g, int(spec["k"]), rng)
+        stats["draws"] += 1
+        cls = "dense" if q.avg_degree >= 3.0 else "sparse"
+        if len(got[cls]) >= quota[cls]:
+            stats["skipped_full"] += 1
+            continue
+        d = q.to_dict()
+        if cls == "sparse":
+            if not cf.is_tree_with_distinct_labels(q):
+                stats["sparse_not_distinct_label_tree"] += 1
+                continue
+            try:
+                c = exact.count(q)
+            except OverflowError:
+                c = None
+            if c is None or c > count_cap:
+                stats["sparse_over_cap"] += 1
+                continue
+            d.update(draw=draw, kind=cls, count=c, expected_from="tree_dp")
+        else:
+            if stats["dense_tried"] >= dense_tries:
+                stats["dense_not_tried"] += 1
+                continue
+            stats["dense_tried"] += 1
+            t = time.time()
+            r = oracle.match(g, q, node_budget=budget, threads=threads)
+            dt = time.time() - t
+            if r.status != oracle.OK:
+                stats["dense_over_budget"] += 1
+                print(f"draw {draw} dense m_q={q.m_q} over budget ({dt:.1f}s)", flush=True)
+                continue
+            d.update(draw=draw, kind=cls, count=r.count, nodes=r.nodes, oracle_s=round(dt, 3), expected_from="oracle")
+        got[cls].append(d)
+        print(f"draw {draw} {cls} m_q={q.m_q} count={d['count']} "
+              f"[{len(got['sparse'])}/{quota['sparse']} sparse, {len(got['dense'])}/{quota['dense']} dense]",
+              flush=True)
+    queries = sorted(got["sparse"] + got["dense"], key=lambda d: d["draw"])
+    for i, d in enumerate(queries):
+        d["qid"] = i
+    stats["seconds"] = round(time.time() - t_start, 1)
+    write(w["name"], {
+        "workload": w,
+        "graph_summary": g.summary(),
+        "screen": {"sparse_rule": "tree query with pairwise-distinct labels and at most count_cap embeddings "
+                                  "(exact count: labelled tree homomorphism DP)",
+                   "dense_rule": "oracle finishes within node_budget visited partial embeddings",
+                   "count_cap": count_cap, "node_budget": budget, "max_draws": max_draws,
+                   "dense_tries": dense_tries, **stats, "short": {c: quota[c] - len(got[c]) for c in quota}},
+        "oracle": {"threads": threads or oracle.num_cores()},
+        "queries": queries,
+    })
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("name", choices=sorted(ALL))
+    ap.add_argument("--budget", type=int, default=200_000_000)
+    ap.add_argument("--max-draws", type=int, default=200_000)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--count-cap", type=int, default=20_000_000_000)
+    ap.add_argument("--dense-tries", type=int, default=100)
+    a = ap.parse_args()
+    w = ALL[a.name]
+    if "sizes" in w["queries"]:
+        make_small(w)
+    else:
+        make_screened(w, a.budget, a.max_draws, a.threads, a.count_cap, a.dense_tries)
+
+
+if __name__ == "__main__":
+    main()

@@ -19,7 +19,7 @@ from oracle import cst_ref
 import closed_forms as cf
 from synth import make_graph, query_set
 from test_oracle import random_connected_query, random_tiny_graph
-from gpu_common import ctx, gpu_count, gpu_graph, gpu_rows
+from gpu_common import MODES, ctx, gpu_count, gpu_graph, gpu_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -74,11 +74,12 @@ def _c1():
     return make_graph({"kind": "er", "n": 3000, "p": 10 / 2999, "seed": 11, "labels": {"kind": "uniform", "L": 20}})
 
 
-def test_small_config_counts_and_lists():
+@pytest.mark.parametrize("mode", MODES)
+def test_small_config_counts_and_lists(mode):
     g = _c1()
-    G = gpu_graph(g)
-    for i, q in enumerate(query_set(g, [4] * 8, 21)):
-        say(f"small config query {i}: labels {q.qlabel.tolist()} edges {q.qedges.tolist()}")
+    G = gpu_graph(g, mode)
+    for i, q in enumerate(query_set(g, [4] * 8, 21) + query_set(g, [5, 6, 7, 8], 22)):
+        say(f"small config query {i} ({mode}): labels {q.qlabel.tolist()} edges {q.qedges.tolist()}")
         want_n, want_rows = _oracle_rows(g, q)
         n, rows = gpu_rows(G, q)
         assert n == want_n
@@ -102,13 +103,14 @@ def test_candidate_sets_match_reference():
         c.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("seed", range(30))
-def test_random_tiny_graphs(seed):
+def test_random_tiny_graphs(seed, mode):
     rng = np.random.default_rng(1000 + seed)
     g = random_tiny_graph(rng)
     q = random_connected_query(rng, L=int(g.label.max()) + 1)
-    say(f"tiny seed {seed}: n={g.n} k={q.k} m_q={q.m_q}")
-    G = gpu_graph(g)
+    say(f"tiny seed {seed} ({mode}): n={g.n} k={q.k} m_q={q.m_q}")
+    G = gpu_graph(g, mode)
     want_n, want_rows = _oracle_rows(g, q)
     n, rows = gpu_rows(G, q)
     assert n == want_n
@@ -147,9 +149,10 @@ def test_partition_count_matches_reference_rule():
             assert n == oracle.count(g, q)
 
 
-def test_edge_cases_single_vertex_absent_label_and_k2():
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases_single_vertex_absent_label_and_k2(mode):
     g = _c1()
-    G = gpu_graph(g)
+    G = gpu_graph(g, mode)
     for lab in (0, 7, 19):
         n, _ = gpu_count(G, cf.query([lab], []))
         assert n == int((g.label == lab).sum())
@@ -164,28 +167,31 @@ def test_edge_cases_single_vertex_absent_label_and_k2():
         assert n == want_n and rows == want_rows
 
 
-def test_closed_forms_on_gpu():
+@pytest.mark.parametrize("mode", MODES)
+def test_closed_forms_on_gpu(mode):
     from math import perm
 
-    G = gpu_graph(cf.complete(9))
+    G = gpu_graph(cf.complete(9), mode)
     for k in range(1, 7):
-        n, _ = gpu_count(G, cf.clique_query([0] * k))
+        n, _ = gpu_count(G, cf.clique_query([0] * k), partition=mode == "lds")
         assert n == perm(9, k)
-    G = gpu_graph(cf.complete_bipartite(4, 5))
-    assert gpu_count(G, cf.cycle_query(3))[0] == 0
-    assert gpu_count(G, cf.cycle_query(4))[0] == cf.c4_in_complete_bipartite(4, 5)
+    G = gpu_graph(cf.complete_bipartite(4, 5), mode)
+    assert gpu_count(G, cf.cycle_query(3), partition=False)[0] == 0
+    assert gpu_count(G, cf.cycle_query(4), partition=False)[0] == cf.c4_in_complete_bipartite(4, 5)
 
 
-def test_batch_matches_individual_counts():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_individual_counts(mode):
     g = _c1()
-    G = gpu_graph(g)
+    G = gpu_graph(g, mode)
     from paper_2102_10768_amd import cstm
 
     qs = query_set(g, [3, 4, 5, 6] * 3, 71)
-    csts = [cstm.CST(ctx(), G, q.qlabel, q.qedges) for q in qs]
-    for c in csts:
-        c.partition(4096)
-    got = cstm.batch_count(ctx(), csts)
+    csts = [cstm.CST(ctx(mode), G, q.qlabel, q.qedges) for q in qs]
+    for i, c in enumerate(csts):
+        if mode == "lds" or (mode == "auto" and i % 2):
+            c.partition(4096)
+    got = cstm.batch_count(ctx(mode), csts)
     want = [oracle.count(g, q) for q in qs]
     assert got == want
     for c in csts:
