@@ -138,6 +138,8 @@ static void visit(worker_t* w, int depth) {
     const int32_t pv = w->map[c->pivot[depth]];
     for (int64_t e = c->rp[pv]; e < c->rp[pv + 1]; ++e) {
         if (atomic_load_explicit(&c->stop, memory_order_relaxed)) return;
+        /* every scanned adjacency entry is work too, so a long fruitless scan still meets the budget */
+        if (++w->unflushed > FLUSH_MASK) flush_nodes(w);
         const int32_t x = c->col[e];
         if (c->mutate != 3 && c->lab[x] != c->qlab[u]) continue;
         if (c->degfilter) {
@@ -199,8 +201,9 @@ int oracle_num_cores(void) {
  *       to *threads_used.
  *   deadline_s (<= 0: none) and node_budget (0: none): on expiry the call
  *       returns OR_ETIMEOUT and *count_out is a lower bound.  The budget caps
- *       the number of partial embeddings visited (root level included), which is
- *       deterministic, so a budget screen accepts the same queries on any host.
+ *       the work done: partial embeddings visited (root level included) plus
+ *       adjacency entries scanned.  That total is deterministic, so a budget
+ *       screen accepts the same queries on any host; *nodes_out reports it.
  *   rows (may be NULL), cap: with list = 1, the first min(count, cap) rows of the
  *       lexicographically sorted result (row[u] = f(u)); OR_EOVERFLOW when
  *       count > cap (count still exact).

@@ -15,25 +15,69 @@ extern "C" const char* cstm_version(void) { return "cstm 0.1 gfx950"; }
 
 // ---------------------------------------------------------------- device memory
 
+// Device blocks up to 256 MB come from power-of-two size classes and go back
+// to a per-context cache when freed, so repeated CST builds do not pay for
+// hipMalloc/hipFree (hipFree also waits for the whole device).  Callers free a
+// block only after the work that used it has completed on its stream.
+static constexpr int kMaxPooledClass = 28;  // 256 MB
+
 void* cstm_ctx::dmalloc(size_t bytes) {
     void* p = nullptr;
     if (alloc) {
         p = alloc(bytes, user);
         if (!p) throw CstmError{CSTM_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+        return p;
+    }
+    int cls = 8;
+    while (cls <= kMaxPooledClass && (size_t(1) << cls) < bytes) ++cls;
+    if (cls <= kMaxPooledClass) {
+        if (pool.size() <= (size_t)cls) pool.resize(cls + 1);
+        if (!pool[cls].empty()) {
+            p = pool[cls].back();
+            pool[cls].pop_back();
+            return p;
+        }
+        bytes = size_t(1) << cls;
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
+        cls = -1;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        release_pool();  // give cached blocks back and try once more
+        e = hipMalloc(&p, bytes);
         if (e != hipSuccess || !p) {
             (void)hipGetLastError();
             throw CstmError{CSTM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
         }
     }
+    block_class[p] = cls;
     return p;
 }
 
 void cstm_ctx::dfree(void* p) {
     if (!p) return;
-    if (free_fn) free_fn(p, user);
-    else (void)hipFree(p);
+    if (free_fn) {
+        free_fn(p, user);
+        return;
+    }
+    auto it = block_class.find(p);
+    if (it != block_class.end() && it->second >= 0) {
+        pool[it->second].push_back(p);
+        return;
+    }
+    if (it != block_class.end()) block_class.erase(it);
+    (void)hipFree(p);
+}
+
+void cstm_ctx::release_pool() {
+    for (auto& bin : pool) {
+        for (void* p : bin) {
+            block_class.erase(p);
+            (void)hipFree(p);
+        }
+        bin.clear();
+    }
 }
 
 void* cstm_ctx::scratch(size_t bytes) {
@@ -157,6 +201,7 @@ extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->dfree(ctx->tmp);
     ctx->dfree(ctx->enum_ws);
+    ctx->release_pool();
     delete ctx;
 }
 

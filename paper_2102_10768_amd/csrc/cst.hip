@@ -532,6 +532,12 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         P.nt_mask |= 1u << el.from;
         if (P.nt_first < 0) P.nt_first = e;
     }
+    for (int i = 0; i < k; ++i) {
+        PosDesc& P = D.pos[i];
+        bool repeated = false;
+        for (int j = 0; j < k; ++j) repeated |= j != i && D.pos[j].label == P.label;
+        P.need_gid = (repeated || P.nt_mask) ? 1 : 0;
+    }
     c->dev = c->mem.get_n<CstDev>(1);
     HIP_TRY(hipMemcpyAsync(c->dev, &D, sizeof(CstDev), hipMemcpyHostToDevice, s));
     uint64_t bytes = 0;

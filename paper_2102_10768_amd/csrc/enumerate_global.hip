@@ -64,6 +64,8 @@ struct GArgs {
     uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave may wait
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
     int donate_period;          // chunks between donation checks (<= 0: never)
+    int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
+    int64_t donate_last_min;    // smallest last-level remainder worth donating
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -189,6 +191,21 @@ __device__ long long pop_task(const GArgs& A, int lane) {
     return __shfl(slot, 0);
 }
 
+// Combined length of the last-level lists of the survivors (lanes with ok) at level d = k-2.
+__device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, bool ok, int32_t v, int32_t pl, int lane,
+                                     int32_t my_par, const int64_t* my_toff) {
+    const int L = d + 1;
+    const int pk = rl(my_par, L);
+    const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
+    int64_t len = 0;
+    if (ok) {
+        const int32_t x = pk == d ? v : rl(pl, pk);
+        len = toffL[x + 1] - toffL[x];
+    }
+    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) len += __shfl_xor(len, o, CSTM_WAVE);
+    return len;
+}
+
 __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const int lane = lane_id();
     if (A.deadline) A.deadline += now_ticks();  // relative on entry, absolute from here on
@@ -198,7 +215,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const int64_t* my_toff = nullptr;
     const int32_t* my_tadj = nullptr;
     int32_t my_par = -1;
-    uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0;
+    uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0, my_need = 0;
     const CstDev* D = nullptr;
     uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
@@ -232,12 +249,13 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 my_nt = P.nt_mask;
                 my_ntf = (uint32_t)(P.nt_first < 0 ? 0 : P.nt_first);
                 my_u = (uint32_t)P.u;
+                my_need = (A.list || P.need_gid) ? 1u : 0u;
             }
         }
         // level registers: lane d holds level d
         int32_t pl = lane < j ? pre : 0;
         int32_t pg = 0;
-        if (lane < j) pg = my_gid[pl];
+        if (lane < j && my_need) pg = my_gid[pl];
         int64_t lc = 0, le = 0;
         uint64_t lm = 0;
         lc = setl(lc, lo, lane, j);
@@ -259,7 +277,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 const int32_t* gid = (const int32_t*)rlp(my_gid, d);
                 int32_t v = 0;
                 if (val) v = d == 0 ? (int32_t)idx : ((const int32_t*)rlp(my_tadj, d))[idx];
-                const int32_t g = val ? gid[v] : -1;
+                const int32_t g = (val && rl(my_need, d)) ? gid[v] : -1;
                 bool ok = val;
                 uint32_t same = rl(my_same, d);
                 while (same) {
@@ -298,6 +316,81 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                             }
                         }
                     }
+                } else if (d == k - 2 && m && flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff) <= A.flat_max) {
+                    // Last level, flattened: the lists of all survivors of this chunk are
+                    // expanded together, 64 (survivor, candidate) pairs per round, so short
+                    // lists do not leave lanes idle and no survivor needs a level of its own.
+                    const int L = k - 1;
+                    const int pk = rl(my_par, L);
+                    const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
+                    const int32_t* tadjL = (const int32_t*)rlp(my_tadj, L);
+                    const int32_t* gidL = (const int32_t*)rlp(my_gid, L);
+                    const bool needL = rl(my_need, L) != 0;
+                    const uint32_t sameL = rl(my_same, L), ntL = rl(my_nt, L), ntfL = rl(my_ntf, L);
+                    int64_t b0 = 0, len = 0;
+                    if (ok) {
+                        const int32_t x = pk == d ? v : rl(pl, pk);
+                        b0 = toffL[x];
+                        len = toffL[x + 1] - b0;
+                    }
+                    int64_t incl = len;  // inclusive prefix over lanes
+                    for (int o = 1; o < CSTM_WAVE; o <<= 1) {
+                        const int64_t y = __shfl_up(incl, o, CSTM_WAVE);
+                        if (lane >= o) incl += y;
+                    }
+                    const int64_t total = __shfl(incl, CSTM_WAVE - 1);
+                    for (int64_t t0 = 0; t0 < total; t0 += CSTM_WAVE) {
+                        const int64_t t = t0 + lane;
+                        const bool val2 = t < total;
+                        // owner lane: first lane whose inclusive prefix exceeds t
+                        int lo2 = 0, hi2 = CSTM_WAVE - 1;
+                        while (lo2 < hi2) {
+                            const int mid = (lo2 + hi2) >> 1;
+                            if (__shfl(incl, mid) > t) hi2 = mid;
+                            else lo2 = mid + 1;
+                        }
+                        const int sl = lo2;
+                        const int64_t start = __shfl(incl, sl) - __shfl(len, sl);
+                        const int64_t bs = __shfl(b0, sl);
+                        const int32_t vs = __shfl(v, sl), gs = __shfl(g, sl);
+                        int32_t v2 = 0;
+                        if (val2) v2 = tadjL[bs + (t - start)];
+                        const int32_t g2 = (val2 && needL) ? gidL[v2] : -1;
+                        bool ok2 = val2;
+                        uint32_t same2 = sameL;
+                        while (same2) {
+                            const int jj = __ffs(same2) - 1;
+                            same2 &= same2 - 1;
+                            ok2 = ok2 && g2 != (jj == d ? gs : rl(pg, jj));
+                        }
+                        uint32_t nt2 = ntL, e2 = ntfL;
+                        while (nt2) {
+                            const int jj = __ffs(nt2) - 1;
+                            nt2 &= nt2 - 1;
+                            const NtDesc& N = D->nt[e2++];
+                            const int32_t x = jj == d ? vs : rl(pl, jj);
+                            if (ok2) ok2 = contains(N.adj_gid, N.off[x], N.off[x + 1], g2);
+                        }
+                        const uint64_t m2 = __ballot(ok2);
+                        const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2));
+                        nN += nv2;
+                        nM += nv2 * (uint64_t)__popc(ntL);
+                        cnt += (uint64_t)__popcll(m2);
+                        if (A.list && m2) {
+                            unsigned long long base = 0;
+                            if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m2));
+                            base = __shfl(base, 0);
+                            if (ok2) {
+                                const uint64_t r = base + (uint64_t)mbcnt(m2);
+                                if (r < A.cap) {
+                                    int32_t* row = A.rows + r * (uint64_t)k;
+                                    for (int i = 0; i < k; ++i)
+                                        row[rl(my_u, i)] = i == L ? g2 : (i == d ? gs : rl(pg, i));
+                                }
+                            }
+                        }
+                    }
+                    nF += (uint64_t)__popcll(m);
                 } else if (m) {
                     M = m;
                     nF += (uint64_t)__popcll(m);
@@ -323,8 +416,9 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                         // shallowest open level first: its untouched list remainder, or
                         // (above the current level) the survivors not yet descended into,
                         // given away as a range the receiver re-checks
-                        for (int dd = j; dd <= d && dd < k - 1; ++dd) {
+                        for (int dd = j; dd <= d; ++dd) {
                             const int64_t c2 = rl(lc, dd), e2 = rl(le, dd);
+                            if (dd == k - 1 && e2 - c2 < A.donate_last_min) break;
                             if (c2 < e2) {
                                 if (push_task(A, q, dd, c2, e2, pl, lane)) {
                                     le = setl(le, c2, lane, dd);
@@ -355,7 +449,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
             const int64_t chunk = rl(lc, d) - (int64_t)CSTM_WAVE;
             const int32_t v =
                 d == 0 ? (int32_t)(chunk + b) : ((const int32_t*)rlp(my_tadj, d))[chunk + b];
-            const int32_t g = ((const int32_t*)rlp(my_gid, d))[v];
+            const int32_t g = rl(my_need, d) ? ((const int32_t*)rlp(my_gid, d))[v] : 0;
             pl = setl(pl, v, lane, d);
             pg = setl(pg, g, lane, d);
             ++d;
@@ -481,6 +575,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
     A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
     A.donate_period = ctx->tune.hbm_donate_period;
+    A.flat_max = 64 * 32;
+    A.donate_last_min = 4096;
     k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, nq,
                                                                   total);
     HIP_TRY(hipGetLastError());

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "cstm.h"
@@ -67,6 +68,10 @@ struct cstm_ctx {
     // reusable temporary storage for library scans and sorts
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
+    // cache of freed device blocks by power-of-two size class (hipMalloc path only)
+    std::vector<std::vector<void*>> pool;
+    std::unordered_map<void*, int> block_class;
+    void release_pool();
 
     void* dmalloc(size_t bytes);
     void dfree(void* p);
@@ -131,6 +136,8 @@ struct PosDesc {
     uint32_t nt_mask;    // earlier positions joined to i by a non-tree edge
     int32_t nt_first;    // first NtDesc whose later end is i
     int32_t label;
+    int32_t need_gid;    // 1: checks at i read data-vertex ids (repeated label or non-tree edge)
+    int32_t pad;
 };
 
 // A non-tree query edge between positions a < b, lists over C(O[a]) into C(O[b]).

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -184,6 +185,8 @@ class Context:
         _check(lib.cstm_ctx_create(device, alloc, free, None, ctypes.byref(t), ctypes.byref(h)))
         self.handle = h
         self.device = device
+        # graphs and CSTs made in this context; closed before it (they return memory to it)
+        self._children = weakref.WeakSet()
 
     @property
     def tune(self) -> dict:
@@ -210,6 +213,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for child in sorted(list(self._children), key=lambda c: isinstance(c, Graph)):
+                child.close()
             load_library().cstm_ctx_destroy(self.handle)
             self.handle = None
 
@@ -252,6 +257,7 @@ class Graph:
         _check(lib.cstm_graph_load(ctx.handle, n, nnz, ptrs[0], ptrs[1], ptrs[2], int(on_device),
                                    _stream_ptr(stream) if on_device else None, ctypes.byref(h)))
         self.handle = h
+        ctx._children.add(self)
         if not on_device:
             self._tensors = None
 
@@ -286,6 +292,7 @@ class CST:
         _check(lib.cstm_cst_build(ctx.handle, graph.handle, self.k, ql.ctypes.data, int(qe.shape[0]),
                                   qe.ctypes.data if qe.size else None, _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
+        ctx._children.add(self)
 
     def partition(self, budget_bytes: int = 0, max_list_len: int = 0) -> int:
         n = ctypes.c_int64()
@@ -317,15 +324,19 @@ class CST:
                                              _stream_ptr(stream)))
         return c.value
 
-    def list(self, cap: int, stream=None):
-        """Returns (count, rows) with rows a (min(count, cap), k) int32 CUDA tensor; raises on overflow."""
+    def list(self, cap: int, stream=None, allow_overflow: bool = False):
+        """Returns (count, rows): rows is a (min(count, cap), k) int32 CUDA tensor.
+
+        Raises on overflow (count > cap) unless ``allow_overflow``; the count is exact either way.
+        """
         import torch
 
         rows = torch.empty((max(cap, 1), self.k), dtype=torch.int32, device=f"cuda:{self.ctx.device}")
         c, w = ctypes.c_uint64(), ctypes.c_uint64()
         st = load_library().cstm_enumerate(self.handle, 1, rows.data_ptr(), int(cap), ctypes.byref(c),
                                            ctypes.byref(w), _stream_ptr(stream))
-        _check(st)
+        if not (allow_overflow and st == EOVERFLOW):
+            _check(st)
         return c.value, rows[: w.value]
 
     def times(self) -> dict:
