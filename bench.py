@@ -26,6 +26,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def measured_traffic():
+    """HBM bytes per launch of the enumeration kernel from the committed counter
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2102_10768_amd", "csrc", "enumerate_global.hip")
+    prof = os.path.join(ROOT, "profiles", "c2_power_law_hbm_counters.md")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(prof):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_prefix") != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def load_workload(name: str):
     path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
     with open(path) as f:
@@ -179,7 +199,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "algorithmic_bytes_per_step": alg_bytes,
             "launches_per_step": launches,
             "avg_launch_ms": kern_ms / max(1, launches),

@@ -19,7 +19,7 @@ SMALL = {
 
 POWER_LAW_1M = {
     "name": "c2",
-    "title": "Chung-Lu 1M vertices, ~16M edges, gamma 2.3, 32 Zipf(1.0) labels; 100 screened 8-vertex queries",
+    "title": "Chung-Lu 1M vertices, 16M edges, gamma 2.3, 32 Zipf(1.0) labels; screened 8-vertex random-walk queries",
     "graph": {"kind": "chung_lu", "n": 1_000_000, "m": 16_000_000, "gamma": 2.3, "seed": 12,
               "labels": {"kind": "zipf", "L": 32, "s": 1.0}},
     # 50 sparse (average query degree < 3) and 50 dense (>= 3) random-walk queries
