@@ -168,6 +168,18 @@ cstm_status cstm_graph_info(const cstm_graph* g, int64_t* n, int64_t* nnz, int32
 cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
                            int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out);
 
+/* Upper bound on the device bytes cstm_cst_build requests for the query
+ * (k, qlabel, m_q, qedges as for cstm_cst_build): the CST of Section IV-A plus
+ * its build-time tables, from the label index alone.  #C(u) is at most the
+ * number of vertices passing the label and degree filter, and a candidate edge
+ * list holds each data edge at most once, so the summed degrees of either
+ * endpoint's filtered candidates bound its entries.  Host-only: no device work,
+ * no allocation.  The context's block cache rounds each request up to a power
+ * of two (up to 256 MB), so device use can reach twice this figure.  Meant for
+ * admission control before building.  CSTM_EINVAL on a malformed query. */
+cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const int32_t* qlabel, int32_t m_q,
+                              const int32_t* qedges, uint64_t* bytes_out);
+
 /* Partition the CST (Section V-B, Algorithm 2) until every partition's
  * on-chip image is at most budget_bytes and its longest list at most
  * max_list_len (0 = no limit); budget_bytes = 0 takes the context's tuning.

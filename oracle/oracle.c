@@ -21,6 +21,10 @@
  *   then smaller id).  Each later vertex is extended from the adjacency list of
  *   its earliest-placed neighbour (the pivot) and checked against all its other
  *   placed neighbours by binary search in G's sorted rows.
+ * Optionally the caller also passes G's rows regrouped by (label, id); then
+ * the pivot's row is scanned only over the entries that carry u's label (a
+ * binary search finds that range), which skips the entries the label test
+ * would reject anyway and changes nothing else.
  * A degree test d_G(v) >= d_q(u) may prune candidates; it is sound because an
  * injective edge-preserving map sends the d_q(u) distinct neighbours of u to
  * distinct neighbours of f(u).  The tests check both settings agree.
@@ -51,6 +55,7 @@ typedef struct {
     const int64_t* rp;
     const int32_t* col;
     const int32_t* lab;
+    const int32_t* lcol;      /* optional: rows regrouped by (label, id)       */
     int k;
     int32_t qlab[OR_MAXK];
     int32_t qdeg[OR_MAXK];
@@ -136,11 +141,29 @@ static void visit(worker_t* w, int depth) {
     }
     const int u = c->order[depth];
     const int32_t pv = w->map[c->pivot[depth]];
-    for (int64_t e = c->rp[pv]; e < c->rp[pv + 1]; ++e) {
+    const int32_t* row = c->col;
+    int64_t e0 = c->rp[pv], e1 = c->rp[pv + 1];
+    if (c->lcol) {
+        /* the entries of label qlab[u] form one run of the regrouped row */
+        row = c->lcol;
+        int64_t lo = e0, hi = e1;
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (c->lab[row[mid]] < c->qlab[u]) lo = mid + 1; else hi = mid;
+        }
+        e0 = lo;
+        hi = e1;
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (c->lab[row[mid]] <= c->qlab[u]) lo = mid + 1; else hi = mid;
+        }
+        e1 = lo;
+    }
+    for (int64_t e = e0; e < e1; ++e) {
         if (atomic_load_explicit(&c->stop, memory_order_relaxed)) return;
         /* every scanned adjacency entry is work too, so a long fruitless scan still meets the budget */
         if (++w->unflushed > FLUSH_MASK) flush_nodes(w);
-        const int32_t x = c->col[e];
+        const int32_t x = row[e];
         if (c->mutate != 3 && c->lab[x] != c->qlab[u]) continue;
         if (c->degfilter) {
             int64_t d = c->rp[x + 1] - c->rp[x];
@@ -195,6 +218,8 @@ int oracle_num_cores(void) {
  *
  *   n, row_ptr[n+1], col[row_ptr[n]], label[n]: G as CSR, rows sorted, simple,
  *       symmetric (the caller guarantees this; it is not re-checked here).
+ *   lcol (may be NULL): the same rows, each regrouped by (label, id); used
+ *       only to find a pivot's neighbours of one label.
  *   k, qlabel[k], m_q, qedges[2*m_q]: q with query ids 0..k-1.
  *   degree_filter: 1 prunes candidates with d_G(v) < d_q(u).
  *   nthreads: worker threads, 0 = all online cores; the number used is written
@@ -211,7 +236,7 @@ int oracle_num_cores(void) {
  *       that the tests can show their pins catch it.
  */
 int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const int32_t* label,
-                 int32_t k, const int32_t* qlabel, int32_t m_q, const int32_t* qedges,
+                 const int32_t* lcol, int32_t k, const int32_t* qlabel, int32_t m_q, const int32_t* qedges,
                  int degree_filter, int nthreads, double deadline_s, uint64_t node_budget,
                  int list, int32_t* rows, uint64_t cap, int mutate,
                  uint64_t* count_out, uint64_t* nodes_out, uint64_t* rows_written, int* threads_used) {
@@ -221,7 +246,7 @@ int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const in
     if (k < 1 || k > OR_MAXK || n < 0 || m_q < 0) return OR_EINVAL;
     ctx_t* c = (ctx_t*)calloc(1, sizeof(ctx_t));
     if (!c) return OR_ENOMEM;
-    c->n = n; c->rp = row_ptr; c->col = col; c->lab = label; c->k = k;
+    c->n = n; c->rp = row_ptr; c->col = col; c->lab = label; c->lcol = lcol; c->k = k;
     c->degfilter = degree_filter; c->mutate = mutate; c->list = list;
     c->node_budget = node_budget;
     c->deadline = deadline_s > 0 ? now_s() + deadline_s : 0;

@@ -28,6 +28,7 @@ void* cstm_ctx::dmalloc(size_t bytes) {
         if (!p) throw CstmError{CSTM_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
         return p;
     }
+    std::lock_guard<std::mutex> lk(pool_mu);
     int cls = 8;
     while (cls <= kMaxPooledClass && (size_t(1) << cls) < bytes) ++cls;
     if (cls <= kMaxPooledClass) {
@@ -61,6 +62,7 @@ void cstm_ctx::dfree(void* p) {
         free_fn(p, user);
         return;
     }
+    std::lock_guard<std::mutex> lk(pool_mu);
     auto it = block_class.find(p);
     if (it != block_class.end() && it->second >= 0) {
         pool[it->second].push_back(p);
@@ -124,6 +126,7 @@ static int64_t exclusive_scan_impl(cstm_ctx* ctx, const T* in, T* out, int64_t n
         return 0;
     }
     size_t tmp_bytes = 0;
+    std::lock_guard<std::mutex> lk(ctx->scratch_mu);
     HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, out + 1, (int)n, s));
     void* tmp = ctx->scratch(tmp_bytes);
     HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out + 1, (int)n, s));
@@ -201,7 +204,10 @@ extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->dfree(ctx->tmp);
     ctx->dfree(ctx->enum_ws);
-    ctx->release_pool();
+    {
+        std::lock_guard<std::mutex> lk(ctx->pool_mu);
+        ctx->release_pool();
+    }
     delete ctx;
 }
 

@@ -373,6 +373,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
 // run at most one launch of each kind, and return per-CST counts.
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
                         uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(ctx->enum_mu);
     const cstm_tune& T = ctx->tune;
     std::vector<cstm_cst*> lds_q, hbm_q;
     std::vector<int> lds_slot, hbm_slot;

@@ -102,6 +102,15 @@ __global__ void k_make_keys(const int64_t* __restrict__ row_ptr, const int32_t* 
     }
 }
 
+__global__ void k_perm_degrees(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ perm, int64_t n,
+                               int64_t* __restrict__ out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t v = perm[i];
+        out[i] = row_ptr[v + 1] - row_ptr[v];
+    }
+}
+
 __global__ void k_ranks(const int32_t* __restrict__ perm, const int32_t* __restrict__ label,
                         const int64_t* __restrict__ label_ptr, int64_t n, uint64_t* __restrict__ lab_rank) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -212,6 +221,7 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
             int end_bit = 32;
             while (end_bit < 64 && ((uint64_t)L >> (end_bit - 32)) > 0) ++end_bit;
             size_t tb = 0;
+            std::lock_guard<std::mutex> lk(ctx->scratch_mu);
             HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys2, ids, g->perm, (int)n, 0, end_bit, s));
             void* tmp = ctx->scratch(tb);
             HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys, keys2, ids, g->perm, (int)n, 0, end_bit, s));
@@ -229,6 +239,21 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipMemcpyAsync(g->deg_at_least.data(), dal, g->deg_at_least.size() * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            // degree prefix sums in label-index order, for footprint estimates
+            int64_t* pd = (int64_t*)keys;  // n int64 entries, free again
+            int64_t* ps = (int64_t*)keys2;
+            k_perm_degrees<<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->row_ptr, g->perm, n, pd);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(s));
+            g->deg_prefix.assign((size_t)n + 1, 0);
+            {
+                size_t tb2 = 0;
+                HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, pd, ps, (int)n, s));
+                void* tmp2 = ctx->scratch(tb2);
+                HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp2, tb2, pd, ps, (int)n, s));
+                HIP_TRY(hipMemcpyAsync(g->deg_prefix.data() + 1, ps, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
             g->mem.release(keys);
             g->mem.release(keys2);
             g->mem.release(ids);
@@ -239,6 +264,48 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
     });
     if (st != CSTM_OK && g) delete g;
     return st;
+}
+
+extern "C" cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const int32_t* qlabel, int32_t m_q,
+                                         const int32_t* qedges, uint64_t* bytes_out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(g && bytes_out, CSTM_EINVAL, "NULL argument");
+        CSTM_REQUIRE(k >= 1 && k <= CSTM_MAX_K && qlabel, CSTM_EINVAL, "bad query");
+        CSTM_REQUIRE(m_q >= 0 && (m_q == 0 || qedges), CSTM_EINVAL, "bad query edges");
+        int deg[CSTM_MAX_K] = {};
+        for (int e = 0; e < m_q; ++e) {
+            int a = qedges[2 * e], b = qedges[2 * e + 1];
+            CSTM_REQUIRE(a >= 0 && a < k && b >= 0 && b < k && a != b, CSTM_EINVAL, "bad query edge");
+            deg[a]++;
+            deg[b]++;
+        }
+        int64_t c0[CSTM_MAX_K];
+        uint64_t sdeg[CSTM_MAX_K];
+        uint64_t bytes = 0, max_c0 = 0;
+        for (int u = 0; u < k; ++u) {
+            CSTM_REQUIRE(qlabel[u] >= 0, CSTM_EINVAL, "negative query label");
+            c0[u] = g->count_ge(qlabel[u], deg[u]);
+            sdeg[u] = 0;
+            if (c0[u] > 0) {
+                int64_t lo = g->label_ptr[qlabel[u]];
+                sdeg[u] = (uint64_t)(g->deg_prefix[lo + c0[u]] - g->deg_prefix[lo]);
+            }
+            if ((uint64_t)c0[u] > max_c0) max_c0 = (uint64_t)c0[u];
+            // candidate array and rank table (C(u) is a subset of the filtered label prefix)
+            bytes += 8ull * (uint64_t)c0[u];
+        }
+        // scan, flag, per-owner counts and the path-count vectors of one leaf path
+        bytes += (24ull + 8ull * (uint64_t)k) * (max_c0 + 1);
+        // every candidate edge list: offsets over its owner, entries (ids and, for
+        // non-tree lists, global ids); an edge (v, w) with v in C(a), w in C(b)
+        // appears once, so either side's degree sum bounds the entries
+        for (int e = 0; e < m_q; ++e) {
+            int a = qedges[2 * e], b = qedges[2 * e + 1];
+            uint64_t ent = sdeg[a] < sdeg[b] ? sdeg[a] : sdeg[b];
+            bytes += 8ull * (max_c0 + 1) + 8ull * ent;
+        }
+        *bytes_out = bytes + 4096;  // descriptor and small flags
+    });
 }
 
 extern "C" void cstm_graph_free(cstm_graph* g) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -72,6 +73,12 @@ struct cstm_ctx {
     std::vector<std::vector<void*>> pool;
     std::unordered_map<void*, int> block_class;
     void release_pool();
+    // A context may be used from several host threads (e.g. one building CSTs
+    // while another enumerates): the block cache, the scan scratch and the
+    // enumeration workspace each have a lock.
+    std::mutex pool_mu;
+    std::mutex scratch_mu;  // held for the whole use of `tmp`
+    std::mutex enum_mu;     // held for a whole enumeration launch
 
     void* dmalloc(size_t bytes);
     void dfree(void* p);
@@ -114,6 +121,8 @@ struct cstm_graph {
     std::vector<int64_t> label_ptr;  // host, num_labels + 1
     // host: count of vertices of label l with degree >= d, d = 0..CSTM_MAX_K
     std::vector<int64_t> deg_at_least;
+    // host: prefix sums of degrees in label-index order (n + 1 entries)
+    std::vector<int64_t> deg_prefix;
 
     int64_t count_ge(int32_t l, int32_t d) const {
         if (l < 0 || l >= num_labels) return 0;

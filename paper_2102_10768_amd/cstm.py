@@ -87,7 +87,7 @@ EXPORTS = [
     "cstm_graph_load", "cstm_graph_free", "cstm_graph_info",
     "cstm_cst_build", "cstm_cst_partition", "cstm_cst_info_get", "cstm_cst_candidates",
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
-    "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats",
+    "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
 ]
 
 _lib = None
@@ -128,6 +128,7 @@ def load_library():
                                 ctypes.POINTER(ctypes.c_double)]),
         "cstm_cst_free": (None, [P]),
         "cstm_ctx_last_enum_stats": (st, [P, ctypes.POINTER(cstm_enum_stats)]),
+        "cstm_cst_estimate": (st, [P, I32, P, I32, P, ctypes.POINTER(U64)]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -260,6 +261,15 @@ class Graph:
         ctx._children.add(self)
         if not on_device:
             self._tensors = None
+
+    def estimate_bytes(self, qlabel, qedges) -> int:
+        """Upper bound on the device bytes a CST build for this query would use."""
+        ql = np.ascontiguousarray(qlabel, dtype=np.int32)
+        qe = np.ascontiguousarray(np.asarray(qedges, dtype=np.int32).reshape(-1, 2))
+        out = ctypes.c_uint64()
+        _check(load_library().cstm_cst_estimate(self.handle, int(ql.shape[0]), ql.ctypes.data, int(qe.shape[0]),
+                                                qe.ctypes.data if qe.size else None, ctypes.byref(out)))
+        return out.value
 
     def info(self) -> dict:
         n, nnz, L, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()

@@ -133,6 +133,51 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
     })
 
 
+def make_batch(w: dict, budget: int, max_draws: int, threads: int):
+    """Batch workload: query sizes uniform in [k_min, k_max]; each draw is kept when
+    the oracle finishes it within the work budget (the same deterministic screen)."""
+    g = make_graph(w["graph"])
+    print("graph", g.summary(), flush=True)
+    lcol = oracle.label_grouped_col(g)
+    spec = w["queries"]
+    rng = _rng(spec["seed"], STREAM_QUERIES)
+    want = int(spec["count"])
+    out = []
+    stats = {"draws": 0, "over_budget": 0}
+    t_start = time.time()
+    for draw in range(max_draws):
+        if len(out) >= want:
+            break
+        k = int(rng.integers(int(spec["k_min"]), int(spec["k_max"]) + 1))
+        q = random_walk_query(g, k, rng)
+        stats["draws"] += 1
+        t = time.time()
+        r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol)
+        dt = time.time() - t
+        if (draw + 1) % 250 == 0:
+            print(f"{draw + 1} draws, {len(out)} kept ({time.time() - t_start:.0f}s)", flush=True)
+        if r.status != oracle.OK:
+            stats["over_budget"] += 1
+            continue
+        d = q.to_dict()
+        d.update(draw=draw, qid=len(out), count=r.count, nodes=r.nodes, oracle_s=round(dt, 4),
+                 expected_from="oracle")
+        out.append(d)
+        if len(out) % 50 == 0:
+            print(f"{len(out)}/{want} after {draw + 1} draws ({time.time() - t_start:.0f}s)", flush=True)
+    stats["seconds"] = round(time.time() - t_start, 1)
+    write(w["name"], {
+        "workload": w,
+        "graph_summary": g.summary(),
+        "screen": {"rule": "oracle (label-grouped rows) finishes within node_budget work units",
+                   "node_budget": budget, "sizes_kept": {str(k): sum(1 for d in out if len(d["qlabel"]) == k)
+                                                         for k in range(int(spec["k_min"]), int(spec["k_max"]) + 1)},
+                   "max_draws": max_draws, **stats, "short": want - len(out)},
+        "oracle": {"threads": threads or oracle.num_cores()},
+        "queries": out,
+    })
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("name", choices=sorted(ALL))
@@ -145,6 +190,8 @@ def main():
     w = ALL[a.name]
     if "sizes" in w["queries"]:
         make_small(w)
+    elif "k_min" in w["queries"]:
+        make_batch(w, a.budget, a.max_draws, a.threads)
     else:
         make_screened(w, a.budget, a.max_draws, a.threads, a.count_cap, a.dense_tries)
 

@@ -121,3 +121,44 @@ def test_small_config_lists_match_oracle_in_lds_mode():
         assert n == r.count == d["count"]
         assert sorted(tuple(int(x) for x in row) for row in rows.cpu().numpy()) == [
             tuple(int(x) for x in row) for row in r.rows]
+
+
+def test_deadline_stops_a_launch_and_the_context_recovers():
+    """A 1 ms deadline, set from the host, ends the enumeration kernel early with ETIMEOUT."""
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c2")
+    g, G = _graph("c2", W, "hbm")
+    heavy = max(W["queries"], key=lambda d: d["count"])
+    q = Query.from_dict(heavy)
+    c = cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges)
+    ctx("hbm").tune = {"deadline_ms": 1}
+    try:
+        with pytest.raises(cstm.CstmError) as ei:
+            c.count()
+        assert ei.value.status == cstm.ETIMEOUT
+    finally:
+        ctx("hbm").tune = {"deadline_ms": 0}
+    light = min(W["queries"], key=lambda d: d["count"])
+    q2 = Query.from_dict(light)
+    c2 = cstm.CST(ctx("hbm"), G, q2.qlabel, q2.qedges)
+    assert c2.count() == light["count"]
+    c.close()
+    c2.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_footprint_estimate_bounds_the_built_cst(name):
+    """The label-index estimate never falls below the CST bytes actually built."""
+    from paper_2102_10768_amd import cstm
+
+    W = _load(name)
+    g, G = _graph(name, W, "hbm")
+    for d in W["queries"][:12]:
+        q = Query.from_dict(d)
+        est = G.estimate_bytes(q.qlabel, q.qedges)
+        c = cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges)
+        built = c.info()["bytes"]
+        c.close()
+        say(f"{name} query {d.get('qid')}: built {built} B, estimate {est} B")
+        assert built <= est

@@ -58,12 +58,14 @@ def test_matches_bruteforce_on_tiny_graphs(seed):
     g = random_tiny_graph(rng)
     q = random_connected_query(rng, L=int(g.label.max()) + 1)
     want = bruteforce.embeddings(g, q)
+    lcol = oracle.label_grouped_col(g)
     for degf in (True, False):
         for threads in (1, 3):
-            r = oracle.match(g, q, list_rows=True, cap=20000, degree_filter=degf, threads=threads)
-            assert r.status == oracle.OK
-            assert r.count == len(want)
-            assert rows_of(r) == want
+            for lc in (None, lcol):
+                r = oracle.match(g, q, list_rows=True, cap=20000, degree_filter=degf, threads=threads, lcol=lc)
+                assert r.status == oracle.OK
+                assert r.count == len(want)
+                assert rows_of(r) == want
 
 
 def test_listing_cap_reports_overflow_with_exact_count():
@@ -244,6 +246,23 @@ def test_degree_filter_and_thread_count_do_not_change_results():
         b = oracle.match(g, q, degree_filter=False, threads=0, list_rows=True)
         assert a.count == b.count
         assert rows_of(a) == rows_of(b)
+
+
+def test_label_grouped_rows_are_regrouped_rows_and_change_no_result():
+    g = _c1_graph()
+    lcol = oracle.label_grouped_col(g)
+    for v in range(0, g.n, 97):
+        a, b = g.row_ptr[v], g.row_ptr[v + 1]
+        row = lcol[a:b]
+        assert sorted(row.tolist()) == g.col[a:b].tolist()
+        keys = [(int(g.label[x]), int(x)) for x in row]
+        assert keys == sorted(keys)
+    for q in query_set(g, [4, 5, 6] * 2, 37):
+        a = oracle.match(g, q, list_rows=True)
+        b = oracle.match(g, q, list_rows=True, lcol=lcol, threads=2)
+        assert a.status == b.status == oracle.OK
+        assert a.count == b.count and rows_of(a) == rows_of(b)
+        assert b.nodes <= a.nodes
 
 
 def test_node_budget_is_deterministic_and_reports_timeout():
