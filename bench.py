@@ -1,13 +1,15 @@
 """Benchmark: embeddings/sec of CST subgraph matching on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2] [--no-autotune]
 
 One step runs the whole matching path for every query of the workload: CST
 construction on the device, the partition check, and enumeration (counting).
-The plain form issues one query per launch; the batched form (reported
-beside it) builds all CSTs and counts them in one persistent launch.  Counts
-are checked against the expected values stored with the workload.  The graph
-is generated from its seed and made resident before timing starts.
+The plain form issues one query per launch with the library's default launch
+parameters; the batched form (reported beside it) builds all CSTs and counts
+them in one persistent launch, with launch parameters chosen by the autotuner
+on a seeded calibration subset.  Counts are checked against the expected
+values stored with the workload.  The graph is generated from its seed and
+made resident before timing starts.
 
 Prints one JSON line (see the keys below); exits 1 if a count is wrong.
 """
@@ -62,6 +64,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="batched form with the default launch parameters")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
@@ -135,7 +138,20 @@ def main():
     ms_per_step = 1e3 * elapsed / a.steps
     value = total * a.steps / elapsed
 
-    # batched form on the same queries
+    # enumeration-kernel roofline: one stats pass (counters on), timing from the timed steps
+    ctx.tune = {"collect_stats": 1}
+    stats_rows = []
+    plain_step(stats_rows)
+    ctx.tune = {"collect_stats": 0}
+
+    # batched form on the same queries, launch parameters from the autotuner
+    tuned = None
+    if not a.no_autotune:
+        from paper_2102_10768_amd import autotune
+
+        tuned = autotune.tune(ctx, G, queries, stream=stream,
+                              log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"autotune chose {tuned['choice']}", file=sys.stderr, flush=True)
     btotal, bcounts, _ = batched_step()
     bad_b = [i for i, (x, y) in enumerate(zip(bcounts, expected)) if x != y]
     torch.cuda.synchronize()
@@ -146,11 +162,6 @@ def main():
     torch.cuda.synchronize()
     b_elapsed = time.perf_counter() - tb
 
-    # enumeration-kernel roofline: one stats pass (counters on), timing from the timed steps
-    ctx.tune = {"collect_stats": 1}
-    stats_rows = []
-    plain_step(stats_rows)
-    ctx.tune = {"collect_stats": 0}
     kern_ms = sum(r[1]["kernel_ms"] for r in per_query)
     launches = sum(r[1]["launches"] for r in per_query)
     N = sum(r[1]["extensions"] for r in stats_rows)
@@ -191,6 +202,10 @@ def main():
             "ms_per_step": 1e3 * b_elapsed / bsteps,
             "kernel_ms": bst["kernel_ms"],
             "form": "all CSTs built, then one persistent launch over a device task queue",
+            "vs_plain": (btotal * bsteps / b_elapsed) / value if value else None,
+            "autotune": None if tuned is None else {
+                "choice": tuned["choice"], "calibration": {k: tuned["subset"][k] for k in ("frac", "seed")},
+                "calibration_queries": len(tuned["subset"]["indices"]), "candidates_timed": len(tuned["trials"])},
         },
         "roofline": {
             "kernel": "k_enumerate_global",

@@ -20,7 +20,11 @@
  *     it passes in; the library never frees caller memory.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
  *     that return results to the host synchronise that stream before returning.
- *   - Handles are not thread-safe: use one handle per thread or lock outside.
+ *   - Threads: a context and a loaded graph may be shared by host threads.
+ *     CST builds and enumeration launches from different threads may run at
+ *     the same time on different streams (each launch borrows its own
+ *     workspace).  A CST handle must not be used by two calls at once, and
+ *     cstm_ctx_set_tune must not race with calls in flight on the context.
  *   - Vertex ids and labels are int32, CSR offsets int64, counts uint64.
  */
 #ifndef CSTM_H
@@ -72,12 +76,22 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                                       work through a device task queue,
  *                        CSTM_MODE_AUTO LDS for CSTs the caller partitioned
  *                                       (cstm_cst_partition), else HBM.
- *   max_replication    reserved (limit on partition bytes / CST bytes).
+ *   max_replication    when a launch in LDS mode meets a CST the caller did
+ *                      not partition, it partitions it at part_budget_bytes
+ *                      unless the images would exceed max_replication times
+ *                      the CST's bytes; such a CST is enumerated in HBM mode
+ *                      instead (negative: no limit; default 16).
  *   deadline_ms        HBM mode: stop an enumeration launch after this many
  *                      milliseconds and return CSTM_ETIMEOUT (0 = no limit).
  *   hbm_wgs_per_cu     HBM mode: 256-thread workgroups per compute unit.
  *   hbm_donate_period  HBM mode: chunks a wavefront expands between checks
- *                      for waiting wavefronts (negative: never donate).      */
+ *                      for waiting wavefronts (negative: never donate).
+ *   hbm_flat_max       HBM mode: the last level is expanded as one flat list
+ *                      over all surviving parents when their candidate lists
+ *                      sum to at most this many entries (default 2048;
+ *                      negative: never).
+ *   hbm_donate_last_min HBM mode: smallest remainder of the last level a
+ *                      wavefront hands to a waiting one (default 4096).      */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -92,7 +106,8 @@ typedef struct {
     int32_t deadline_ms;
     int32_t hbm_wgs_per_cu;
     int32_t hbm_donate_period;
-    int32_t reserved;
+    int32_t hbm_flat_max;
+    int32_t hbm_donate_last_min;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).

@@ -97,6 +97,32 @@ void* cstm_ctx::scratch(size_t bytes) {
     return tmp;
 }
 
+void* cstm_ctx::ws_acquire(size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(ws_mu);
+        size_t best = ws_free.size();
+        for (size_t i = 0; i < ws_free.size(); ++i)
+            if (ws_free[i].second >= bytes && (best == ws_free.size() || ws_free[i].second < ws_free[best].second))
+                best = i;
+        if (best < ws_free.size()) {
+            void* p = ws_free[best].first;
+            ws_free.erase(ws_free.begin() + (long)best);
+            return p;
+        }
+    }
+    size_t want = bytes + bytes / 4;
+    void* p = dmalloc(want);
+    std::lock_guard<std::mutex> lk(ws_mu);
+    ws_all.push_back(p);
+    ws_sizes[p] = want;
+    return p;
+}
+
+void cstm_ctx::ws_release(void* p) {
+    std::lock_guard<std::mutex> lk(ws_mu);
+    ws_free.push_back({p, ws_sizes[p]});
+}
+
 void DevArena::release(void* p) {
     for (size_t i = 0; i < blocks.size(); ++i) {
         if (blocks[i] == p) {
@@ -170,6 +196,8 @@ static void apply_defaults(cstm_ctx* c) {
     if (t.deadline_ms < 0) t.deadline_ms = 0;
     if (t.hbm_wgs_per_cu <= 0) t.hbm_wgs_per_cu = 4;
     if (t.hbm_donate_period == 0) t.hbm_donate_period = 64;
+    if (t.hbm_flat_max == 0) t.hbm_flat_max = 2048;
+    if (t.hbm_donate_last_min <= 0) t.hbm_donate_last_min = 4096;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,
@@ -203,7 +231,7 @@ extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->dfree(ctx->tmp);
-    ctx->dfree(ctx->enum_ws);
+    for (void* p : ctx->ws_all) ctx->dfree(p);
     {
         std::lock_guard<std::mutex> lk(ctx->pool_mu);
         ctx->release_pool();
@@ -236,6 +264,7 @@ extern "C" cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out) {
 extern "C" cstm_status cstm_ctx_last_enum_stats(const cstm_ctx* ctx, cstm_enum_stats* out) {
     return cstm_guard([&] {
         CSTM_REQUIRE(ctx && out, CSTM_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(const_cast<cstm_ctx*>(ctx)->ws_mu);
         *out = ctx->last_enum;
     });
 }

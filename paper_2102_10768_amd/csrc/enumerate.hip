@@ -335,13 +335,12 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     A.stats = ctx->tune.collect_stats ? work + 1 : nullptr;
     const int waves = ctx->tune.waves_per_wg;
     const size_t lds = (size_t)cstm_align16(max_blob);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [&] {
         (void)hipFuncSetAttribute((const void*)k_enumerate, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)ctx->lds_per_wg - 64);
         (void)hipGetLastError();
-        attr_set = true;
-    }
+    });
     int64_t grid = (int64_t)ctx->num_cus * ctx->tune.wgs_per_cu;
     grid = std::min<int64_t>(grid, total);
     hipEvent_t ev[2];
@@ -373,8 +372,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
 // run at most one launch of each kind, and return per-CST counts.
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
                         uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
-    std::lock_guard<std::mutex> lk(ctx->enum_mu);
-    const cstm_tune& T = ctx->tune;
+    const cstm_tune T = ctx->tune;
     std::vector<cstm_cst*> lds_q, hbm_q;
     std::vector<int> lds_slot, hbm_slot;
     for (int q = 0; q < nq; ++q) {
@@ -386,8 +384,13 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
             // CST stays in HBM, where the whole GPU shares one query's search
             mode = c->partitioned ? CSTM_MODE_LDS : CSTM_MODE_HBM;
         }
+        if (mode == CSTM_MODE_LDS && !c->partitioned) {
+            // partition at the context's budget, unless the images would replicate
+            // the CST beyond max_replication: then the CST stays in HBM
+            uint64_t cap = T.max_replication > 0 ? (uint64_t)T.max_replication * std::max<uint64_t>(c->bytes, 4096) : 0;
+            if (!cstm_partition_run(c, 0, T.max_list_len, cap)) mode = CSTM_MODE_HBM;
+        }
         if (mode == CSTM_MODE_LDS) {
-            if (!c->partitioned) cstm_partition_run(c, 0, T.max_list_len, 0);
             lds_q.push_back(c);
             lds_slot.push_back(q);
         } else {
@@ -410,7 +413,10 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
     std::vector<unsigned long long> h(nq + 1);
     HIP_TRY(hipMemcpyAsync(h.data(), counts, (nq + 1) * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    ctx->last_enum = st;
+    {
+        std::lock_guard<std::mutex> lk(ctx->ws_mu);
+        ctx->last_enum = st;
+    }
     for (int q = 0; q < nq; ++q) counts_host[q] = h[q];
     if (rows_written) *rows_written = std::min<uint64_t>(h[nq], cap);
 }

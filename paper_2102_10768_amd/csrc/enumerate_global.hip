@@ -514,8 +514,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const unsigned long long total = (unsigned long long)first[nq];
     CSTM_REQUIRE(total < qcap / 2, CSTM_EINVAL, "too many root candidates for the task ring");
     if (total == 0) return;
-    // workspace kept by the context: ring, ready flags, queue state, counters, descriptors
-    // workspace kept by the context, every region 256-byte aligned and sized by sizeof():
+    // workspace lent by the context for this launch, every region 256-byte aligned and sized by sizeof():
     // ring | ready flags | queue state | work counters | descriptors | seed tables | count slots
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t off_ready = up(qcap * sizeof(GTask));
@@ -526,16 +525,12 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const size_t off_slot = up(off_meta + (3 * (size_t)nq + 1) * sizeof(int64_t));
     const size_t need = up(off_slot + (size_t)nq * sizeof(int32_t));
     const size_t ready_b = qcap * sizeof(unsigned int);
-    if (ctx->enum_ws_bytes < need) {
-        HIP_TRY(hipStreamSynchronize(s));
-        ctx->dfree(ctx->enum_ws);
-        ctx->enum_ws = nullptr;
-        ctx->enum_ws_bytes = 0;
-        size_t want = need + need / 4;
-        ctx->enum_ws = ctx->dmalloc(want);
-        ctx->enum_ws_bytes = want;
-    }
-    uint8_t* ws = (uint8_t*)ctx->enum_ws;
+    struct WsHold {
+        cstm_ctx* ctx;
+        void* p;
+        ~WsHold() { ctx->ws_release(p); }
+    } hold{ctx, ctx->ws_acquire(need)};
+    uint8_t* ws = (uint8_t*)hold.p;
     GTask* tasks = (GTask*)ws;
     unsigned int* ready = (unsigned int*)(ws + off_ready);
     GQueue* qu = (GQueue*)(ws + off_qu);
@@ -575,8 +570,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
     A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
     A.donate_period = ctx->tune.hbm_donate_period;
-    A.flat_max = 64 * 32;
-    A.donate_last_min = 4096;
+    A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
+    A.donate_last_min = ctx->tune.hbm_donate_last_min;
     k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, nq,
                                                                   total);
     HIP_TRY(hipGetLastError());
@@ -607,7 +602,10 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     st->edge_checks += h[3];
     st->pushed += h[4];
     st->busy_frac = (h[5] + h[6]) ? (double)h[6] / (double)(h[5] + h[6]) : 0.0;
-    ctx->last_enum = *st;  // kept even when the launch is reported as failed below
+    {
+        std::lock_guard<std::mutex> lk(ctx->ws_mu);
+        ctx->last_enum = *st;  // kept even when the launch is reported as failed below
+    }
     CSTM_REQUIRE(fin.abort.v != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
     CSTM_REQUIRE(!fin.abort.v && fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
 }

@@ -62,10 +62,15 @@ struct cstm_ctx {
     cstm_tune tune{};
     int num_cus = 0;
     int64_t lds_per_wg = 0;
-    cstm_enum_stats last_enum{};
-    // enumeration workspace reused across launches
-    void* enum_ws = nullptr;
-    size_t enum_ws_bytes = 0;
+    cstm_enum_stats last_enum{};  // guarded by ws_mu
+    // HBM-mode enumeration workspaces (task ring and queue state), reused
+    // across launches; one per launch in flight, so launches on different
+    // streams can run at the same time
+    std::vector<std::pair<void*, size_t>> ws_free;
+    std::vector<void*> ws_all;
+    std::unordered_map<void*, size_t> ws_sizes;
+    void* ws_acquire(size_t bytes);
+    void ws_release(void* p);
     // reusable temporary storage for library scans and sorts
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
@@ -74,11 +79,11 @@ struct cstm_ctx {
     std::unordered_map<void*, int> block_class;
     void release_pool();
     // A context may be used from several host threads (e.g. one building CSTs
-    // while another enumerates): the block cache, the scan scratch and the
-    // enumeration workspace each have a lock.
+    // while others enumerate on their own streams): the block cache, the scan
+    // scratch and the workspace list each have a lock.
     std::mutex pool_mu;
     std::mutex scratch_mu;  // held for the whole use of `tmp`
-    std::mutex enum_mu;     // held for a whole enumeration launch
+    std::mutex ws_mu;       // workspace list and last_enum
 
     void* dmalloc(size_t bytes);
     void dfree(void* p);

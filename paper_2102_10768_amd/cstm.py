@@ -40,7 +40,8 @@ class cstm_tune(ctypes.Structure):
         ("deadline_ms", ctypes.c_int32),
         ("hbm_wgs_per_cu", ctypes.c_int32),
         ("hbm_donate_period", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("hbm_flat_max", ctypes.c_int32),
+        ("hbm_donate_last_min", ctypes.c_int32),
     ]
 
 
