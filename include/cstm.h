@@ -81,8 +81,9 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      unless the images would exceed max_replication times
  *                      the CST's bytes; such a CST is enumerated in HBM mode
  *                      instead (negative: no limit; default 16).
- *   deadline_ms        HBM mode: stop an enumeration launch after this many
- *                      milliseconds and return CSTM_ETIMEOUT (0 = no limit).
+ *   deadline_ms        stop an enumeration launch after this many
+ *                      milliseconds and return CSTM_ETIMEOUT, no count
+ *                      reported (0 = no limit; both modes).
  *   hbm_wgs_per_cu     HBM mode: 256-thread workgroups per compute unit.
  *   hbm_donate_period  HBM mode: chunks a wavefront expands between checks
  *                      for waiting wavefronts (negative: never donate).
@@ -91,7 +92,15 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      sum to at most this many entries (default 2048;
  *                      negative: never).
  *   hbm_donate_last_min HBM mode: smallest remainder of the last level a
- *                      wavefront hands to a waiting one (default 4096).      */
+ *                      wavefront hands to a waiting one (default 4096).
+ *   last_level_sum     HBM mode, counting only: when the last query vertex of
+ *                      the matching order has no same-label predecessor and
+ *                      no non-tree edge, every candidate in its tree list is an
+ *                      embedding, so each surviving partial embedding one
+ *                      level up adds the length of that list to the count
+ *                      instead of visiting it (reported in
+ *                      cstm_enum_stats.summed).  1 (default): on; negative:
+ *                      off.  Listing always visits every candidate.          */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -108,6 +117,7 @@ typedef struct {
     int32_t hbm_donate_period;
     int32_t hbm_flat_max;
     int32_t hbm_donate_last_min;
+    int32_t last_level_sum;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).
@@ -119,7 +129,9 @@ typedef struct {
  *   extensions     N: new partial results generated (one per lane per valid
  *                  candidate, all levels after the root);
  *   edge_checks    M: non-tree edge validations executed;
- *   pushed         F: surviving partial results that were extended further.
+ *   pushed         F: surviving partial results that were extended further;
+ *   summed         last-level extensions counted by list length, not
+ *                  visited (tune.last_level_sum; included in extensions).
  * The work counters are zero unless tune.collect_stats was set. */
 typedef struct {
     double kernel_ms;
@@ -131,6 +143,7 @@ typedef struct {
     uint64_t edge_checks;
     uint64_t pushed;
     double busy_frac;    /* HBM mode: share of wavefront time spent expanding  */
+    uint64_t summed;
 } cstm_enum_stats;
 
 /* Facts about a built (and possibly partitioned) CST, for reports and tests. */

@@ -14,7 +14,9 @@ fast that launch runs depends on knobs that leave every count unchanged:
 batch (by default 5 %, seed 301) by coordinate descent: first the mode, then
 each knob of that mode over a short list of values, keeping the best so far.
 Every candidate's counts must equal those of the first setting tried; a
-candidate that changes a count is rejected and reported.  The chosen setting
+candidate that changes a count is rejected and reported.  After the first,
+each candidate runs under a launch deadline of a few times the best time so
+far, so a setting that suits the batch badly costs little.  The chosen setting
 is left applied to the context and returned with the timings.
 """
 
@@ -86,10 +88,15 @@ def tune(ctx, graph, queries, *, frac: float = 0.05, seed: int = 301, repeats: i
     def run(setting):
         nonlocal ref_counts
         full = {**base, **setting}
+        if best_sec < float("inf"):
+            full["deadline_ms"] = max(100, int(4e3 * best_sec) + 1)
         try:
             sec, counts = _time_setting(ctx, graph, sub, full, repeats, stream)
         except cstm.CstmError as e:
-            trials.append({"setting": setting, "error": str(e)})
+            why = "slower than the deadline" if e.status == cstm.ETIMEOUT else str(e)
+            trials.append({"setting": setting, "error": why})
+            if log:
+                log(f"autotune {setting}: {why}")
             return float("inf")
         if ref_counts is None:
             ref_counts = counts
@@ -101,7 +108,7 @@ def tune(ctx, graph, queries, *, frac: float = 0.05, seed: int = 301, repeats: i
             log(f"autotune {setting}: {sec * 1e3:.2f} ms")
         return sec
 
-    best_setting, best_sec = None, float("inf")
+    best_setting, best_sec = None, float("inf")  # read by run() for the deadline
     for mode in modes:
         s = dict(MODE_START[mode])
         sec = run(s)

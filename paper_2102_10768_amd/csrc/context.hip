@@ -198,6 +198,7 @@ static void apply_defaults(cstm_ctx* c) {
     if (t.hbm_donate_period == 0) t.hbm_donate_period = 64;
     if (t.hbm_flat_max == 0) t.hbm_flat_max = 2048;
     if (t.hbm_donate_last_min <= 0) t.hbm_donate_last_min = 4096;
+    if (t.last_level_sum == 0) t.last_level_sum = 1;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,

@@ -31,6 +31,8 @@
 
 namespace {
 
+__device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
+
 struct EnumArgs {
     const uint64_t* blobs;  // absolute image addresses
     const int32_t* qids;    // query slot per image (nullptr: slot 0)
@@ -42,9 +44,24 @@ struct EnumArgs {
     uint64_t cap;
     unsigned long long* row_cursor;
     unsigned long long* stats;  // [images, bytes, N, M, F] or nullptr
+    unsigned long long* stop;   // set to 2 once the deadline has passed
+    uint64_t deadline;          // s_memrealtime ticks (100 MHz) after the start; 0 = none
 };
 
-__device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
+// Deadline check, the same answer in every lane of the wavefront: true once
+// this launch has run past its deadline (any wavefront may have seen it first).
+__device__ inline bool past_deadline(const EnumArgs& A, uint64_t t_end) {
+    if (!A.deadline) return false;
+    int stop = 0;
+    if (lane_id() == 0) {
+        if (__hip_atomic_load(A.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) stop = 1;
+        else if (__builtin_amdgcn_s_memrealtime() > t_end) {
+            atomicExch(A.stop, 2ull);
+            stop = 1;
+        }
+    }
+    return __shfl(stop, 0) != 0;
+}
 
 __device__ inline int mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -83,8 +100,8 @@ __device__ void emit_rows(const EnumArgs& A, uint64_t m, bool mine, int k, int l
 }
 
 // Enumerate the image in LDS with one wavefront; returns the wavefront's count.
-__device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, const EnumArgs& A, uint64_t& nN,
-                                    uint64_t& nM, uint64_t& nF) {
+__device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, const EnumArgs& A, uint64_t t_end,
+                                    uint64_t& nN, uint64_t& nM, uint64_t& nF) {
     const int lane = lane_id();
     const BlobHdr* H = (const BlobHdr*)img;
     const int k = (int)H->k;
@@ -136,7 +153,9 @@ __device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, co
     uint32_t lc = 0, le = 0;
     uint64_t lm = 0;
 
+    uint32_t since_check = 0;
     for (;;) {
+        if (past_deadline(A, t_end)) break;
         uint32_t t0 = 0;
         if (lane == 0) t0 = atomicAdd(s_next, (unsigned int)CSTM_WAVE);
         t0 = (uint32_t)__shfl((int)t0, 0);
@@ -193,6 +212,10 @@ __device__ uint64_t enumerate_image(const uint8_t* img, unsigned int* s_next, co
                     if (cur >= end) {
                         if (--d < 2) break;
                         continue;
+                    }
+                    if (++since_check >= 256u) {
+                        since_check = 0;
+                        if (past_deadline(A, t_end)) return cnt;
                     }
                     // Generator: one extension per lane
                     const uint32_t idx = cur + lane;
@@ -265,8 +288,12 @@ __global__ void k_enumerate(EnumArgs A) {
     __shared__ int64_t s_blob;
     __shared__ unsigned int s_next;
     const int lane = lane_id();
+    const uint64_t t_end = __builtin_amdgcn_s_memrealtime() + A.deadline;
     for (;;) {
-        if (threadIdx.x == 0) s_blob = (int64_t)atomicAdd(A.head, 1u);
+        if (threadIdx.x == 0) {
+            const bool stop = A.deadline && __hip_atomic_load(A.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_blob = stop ? A.n_blobs : (int64_t)atomicAdd(A.head, 1u);
+        }
         __syncthreads();
         const int64_t b = s_blob;
         if (b >= A.n_blobs) break;
@@ -277,7 +304,7 @@ __global__ void k_enumerate(EnumArgs A) {
         if (threadIdx.x == 0) s_next = 0;
         __syncthreads();
         uint64_t nN = 0, nM = 0, nF = 0;
-        const uint64_t c = enumerate_image(img, &s_next, A, nN, nM, nF);
+        const uint64_t c = enumerate_image(img, &s_next, A, t_end, nN, nM, nF);
         if (lane == 0 && c) atomicAdd(&A.counts[A.qids ? A.qids[b] : 0], (unsigned long long)c);
         if (A.stats && lane == 0) {
             if (threadIdx.x == 0) {
@@ -308,8 +335,8 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     CSTM_REQUIRE(total < ((int64_t)1 << 32) - 1, CSTM_EINVAL, "too many partitions for one launch");
     DevArena mem;
     mem.ctx = ctx;
-    unsigned long long* work = mem.get_n<unsigned long long>(6);
-    HIP_TRY(hipMemsetAsync(work, 0, 6 * sizeof(unsigned long long), s));
+    unsigned long long* work = mem.get_n<unsigned long long>(8);
+    HIP_TRY(hipMemsetAsync(work, 0, 8 * sizeof(unsigned long long), s));
     uint64_t* bl = mem.get_n<uint64_t>(total);
     int32_t* qi = mem.get_n<int32_t>(total);
     std::vector<int32_t> hq(total);
@@ -333,6 +360,8 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     A.cap = cap;
     A.row_cursor = row_cursor;
     A.stats = ctx->tune.collect_stats ? work + 1 : nullptr;
+    A.stop = work + 6;
+    A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
     const int waves = ctx->tune.waves_per_wg;
     const size_t lds = (size_t)cstm_align16(max_blob);
     static std::once_flag attr_once;
@@ -355,7 +384,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
-    unsigned long long h[6];
+    unsigned long long h[7];
     HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     st->kernel_ms += kernel_ms;
@@ -366,6 +395,11 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     st->extensions += h[3];
     st->edge_checks += h[4];
     st->pushed += h[5];
+    if (h[6]) {
+        std::lock_guard<std::mutex> lk(ctx->ws_mu);
+        ctx->last_enum = *st;
+    }
+    CSTM_REQUIRE(h[6] != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
 }
 
 // Enumerate nq CSTs: pick LDS images or the HBM-resident CST per the tuning,

@@ -60,12 +60,13 @@ struct GArgs {
     int32_t* rows;
     uint64_t cap;
     unsigned long long* row_cursor;
-    unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks] or nullptr
+    unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks, summed] or nullptr
     uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave may wait
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
     int donate_period;          // chunks between donation checks (<= 0: never)
     int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
     int64_t donate_last_min;    // smallest last-level remainder worth donating
+    int last_sum;               // > 0: count an unconstrained last level by list lengths
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -206,6 +207,108 @@ __device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, boo
     return len;
 }
 
+// Expand level L = d + 1 for every survivor (lanes with ok) of the current
+// level-d chunk at once, 64 (survivor, candidate) pairs per round, so short
+// lists do not leave lanes idle and no survivor needs a descent of its own.
+// L is either the last level (each passing pair is one embedding, written out
+// when listing) or, with sum_next, the second-to-last level of a query whose
+// last level has nothing to check (each passing pair adds the length of its
+// last-level list).  Returns the number of passing pairs.
+__device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D, int k, int d, bool ok, int32_t v,
+                                                int32_t g, int32_t pl, int32_t pg, int lane, int32_t my_par,
+                                                const int64_t* my_toff, const int32_t* my_tadj,
+                                                const int32_t* my_gid, uint32_t my_need, uint32_t my_same,
+                                                uint32_t my_nt, uint32_t my_ntf, uint32_t my_u, bool sum_next,
+                                                uint64_t& cnt, uint64_t& nN, uint64_t& nM, uint64_t& nS) {
+    const int L = d + 1;
+    const int pk = rl(my_par, L);
+    const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
+    const int32_t* tadjL = (const int32_t*)rlp(my_tadj, L);
+    const int32_t* gidL = (const int32_t*)rlp(my_gid, L);
+    const bool needL = rl(my_need, L) != 0;
+    const uint32_t sameL = rl(my_same, L), ntL = rl(my_nt, L), ntfL = rl(my_ntf, L);
+    // with sum_next: where the last level's list owner sits
+    const int pK = sum_next ? rl(my_par, L + 1) : 0;
+    const int64_t* toffK = sum_next ? (const int64_t*)rlp(my_toff, L + 1) : nullptr;
+    int64_t b0 = 0, len = 0;
+    if (ok) {
+        const int32_t x = pk == d ? v : rl(pl, pk);
+        b0 = toffL[x];
+        len = toffL[x + 1] - b0;
+    }
+    int64_t incl = len;  // inclusive prefix over lanes
+    for (int o = 1; o < CSTM_WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(incl, o, CSTM_WAVE);
+        if (lane >= o) incl += y;
+    }
+    const int64_t total = __shfl(incl, CSTM_WAVE - 1);
+    uint64_t passed = 0;
+    for (int64_t t0 = 0; t0 < total; t0 += CSTM_WAVE) {
+        const int64_t t = t0 + lane;
+        const bool val2 = t < total;
+        // owner lane: first lane whose inclusive prefix exceeds t
+        int lo2 = 0, hi2 = CSTM_WAVE - 1;
+        while (lo2 < hi2) {
+            const int mid = (lo2 + hi2) >> 1;
+            if (__shfl(incl, mid) > t) hi2 = mid;
+            else lo2 = mid + 1;
+        }
+        const int sl = lo2;
+        const int64_t start = __shfl(incl, sl) - __shfl(len, sl);
+        const int64_t bs = __shfl(b0, sl);
+        const int32_t vs = __shfl(v, sl), gs = __shfl(g, sl);
+        int32_t v2 = 0;
+        if (val2) v2 = tadjL[bs + (t - start)];
+        const int32_t g2 = (val2 && needL) ? gidL[v2] : -1;
+        bool ok2 = val2;
+        uint32_t same2 = sameL;
+        while (same2) {
+            const int jj = __ffs(same2) - 1;
+            same2 &= same2 - 1;
+            ok2 = ok2 && g2 != (jj == d ? gs : rl(pg, jj));
+        }
+        uint32_t nt2 = ntL, e2 = ntfL;
+        while (nt2) {
+            const int jj = __ffs(nt2) - 1;
+            nt2 &= nt2 - 1;
+            const NtDesc& N = D->nt[e2++];
+            const int32_t x = jj == d ? vs : rl(pl, jj);
+            if (ok2) ok2 = contains(N.adj_gid, N.off[x], N.off[x + 1], g2);
+        }
+        const uint64_t m2 = __ballot(ok2);
+        const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2));
+        nN += nv2;
+        nM += nv2 * (uint64_t)__popc(ntL);
+        passed += (uint64_t)__popcll(m2);
+        if (sum_next) {
+            int64_t lk = 0;
+            if (ok2) {
+                const int32_t xk = pK == L ? v2 : (pK == d ? vs : rl(pl, pK));
+                lk = toffK[xk + 1] - toffK[xk];
+            }
+            for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) lk += __shfl_xor(lk, o, CSTM_WAVE);
+            cnt += (uint64_t)lk;
+            nN += (uint64_t)lk;
+            nS += (uint64_t)lk;
+            continue;
+        }
+        cnt += (uint64_t)__popcll(m2);
+        if (A.list && m2) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m2));
+            base = __shfl(base, 0);
+            if (ok2) {
+                const uint64_t r = base + (uint64_t)mbcnt(m2);
+                if (r < A.cap) {
+                    int32_t* row = A.rows + r * (uint64_t)k;
+                    for (int i = 0; i < k; ++i) row[rl(my_u, i)] = i == L ? g2 : (i == d ? gs : rl(pg, i));
+                }
+            }
+        }
+    }
+    return passed;
+}
+
 __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const int lane = lane_id();
     if (A.deadline) A.deadline += now_ticks();  // relative on entry, absolute from here on
@@ -216,8 +319,9 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const int32_t* my_tadj = nullptr;
     int32_t my_par = -1;
     uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0, my_need = 0;
+    bool sum_last = false;  // this query's last level is counted by list lengths
     const CstDev* D = nullptr;
-    uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, ntasks = 0, ndon = 0;
+    uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
     for (;;) {
         const uint64_t w0 = now_ticks();
@@ -251,6 +355,9 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 my_u = (uint32_t)P.u;
                 my_need = (A.list || P.need_gid) ? 1u : 0u;
             }
+            // the last position has nothing to check when it shares no label with an
+            // earlier one and closes no non-tree edge: its tree list is all results
+            sum_last = A.last_sum > 0 && !A.list && k >= 2 && rl(my_same, k - 1) == 0 && rl(my_nt, k - 1) == 0;
         }
         // level registers: lane d holds level d
         int32_t pl = lane < j ? pre : 0;
@@ -270,6 +377,15 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 if (cur >= end) {
                     if (d == j) break;
                     --d;
+                    continue;
+                }
+                if (d == k - 1 && sum_last && d > 0) {
+                    // a donated remainder of an unconstrained last level
+                    const uint64_t n = (uint64_t)(end - cur);
+                    cnt += n;
+                    nN += n;
+                    nS += n;
+                    lc = setl(lc, end, lane, d);
                     continue;
                 }
                 const int64_t idx = cur + lane;
@@ -316,81 +432,24 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                             }
                         }
                     }
-                } else if (d == k - 2 && m && flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff) <= A.flat_max) {
-                    // Last level, flattened: the lists of all survivors of this chunk are
-                    // expanded together, 64 (survivor, candidate) pairs per round, so short
-                    // lists do not leave lanes idle and no survivor needs a level of its own.
-                    const int L = k - 1;
-                    const int pk = rl(my_par, L);
-                    const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
-                    const int32_t* tadjL = (const int32_t*)rlp(my_tadj, L);
-                    const int32_t* gidL = (const int32_t*)rlp(my_gid, L);
-                    const bool needL = rl(my_need, L) != 0;
-                    const uint32_t sameL = rl(my_same, L), ntL = rl(my_nt, L), ntfL = rl(my_ntf, L);
-                    int64_t b0 = 0, len = 0;
-                    if (ok) {
-                        const int32_t x = pk == d ? v : rl(pl, pk);
-                        b0 = toffL[x];
-                        len = toffL[x + 1] - b0;
+                } else if (d == k - 2 && sum_last) {
+                    // unconstrained last level: every survivor adds its list length
+                    if (m) {
+                        const uint64_t n = (uint64_t)flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff);
+                        cnt += n;
+                        nN += n;
+                        nS += n;
+                        nF += (uint64_t)__popcll(m);
                     }
-                    int64_t incl = len;  // inclusive prefix over lanes
-                    for (int o = 1; o < CSTM_WAVE; o <<= 1) {
-                        const int64_t y = __shfl_up(incl, o, CSTM_WAVE);
-                        if (lane >= o) incl += y;
-                    }
-                    const int64_t total = __shfl(incl, CSTM_WAVE - 1);
-                    for (int64_t t0 = 0; t0 < total; t0 += CSTM_WAVE) {
-                        const int64_t t = t0 + lane;
-                        const bool val2 = t < total;
-                        // owner lane: first lane whose inclusive prefix exceeds t
-                        int lo2 = 0, hi2 = CSTM_WAVE - 1;
-                        while (lo2 < hi2) {
-                            const int mid = (lo2 + hi2) >> 1;
-                            if (__shfl(incl, mid) > t) hi2 = mid;
-                            else lo2 = mid + 1;
-                        }
-                        const int sl = lo2;
-                        const int64_t start = __shfl(incl, sl) - __shfl(len, sl);
-                        const int64_t bs = __shfl(b0, sl);
-                        const int32_t vs = __shfl(v, sl), gs = __shfl(g, sl);
-                        int32_t v2 = 0;
-                        if (val2) v2 = tadjL[bs + (t - start)];
-                        const int32_t g2 = (val2 && needL) ? gidL[v2] : -1;
-                        bool ok2 = val2;
-                        uint32_t same2 = sameL;
-                        while (same2) {
-                            const int jj = __ffs(same2) - 1;
-                            same2 &= same2 - 1;
-                            ok2 = ok2 && g2 != (jj == d ? gs : rl(pg, jj));
-                        }
-                        uint32_t nt2 = ntL, e2 = ntfL;
-                        while (nt2) {
-                            const int jj = __ffs(nt2) - 1;
-                            nt2 &= nt2 - 1;
-                            const NtDesc& N = D->nt[e2++];
-                            const int32_t x = jj == d ? vs : rl(pl, jj);
-                            if (ok2) ok2 = contains(N.adj_gid, N.off[x], N.off[x + 1], g2);
-                        }
-                        const uint64_t m2 = __ballot(ok2);
-                        const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2));
-                        nN += nv2;
-                        nM += nv2 * (uint64_t)__popc(ntL);
-                        cnt += (uint64_t)__popcll(m2);
-                        if (A.list && m2) {
-                            unsigned long long base = 0;
-                            if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m2));
-                            base = __shfl(base, 0);
-                            if (ok2) {
-                                const uint64_t r = base + (uint64_t)mbcnt(m2);
-                                if (r < A.cap) {
-                                    int32_t* row = A.rows + r * (uint64_t)k;
-                                    for (int i = 0; i < k; ++i)
-                                        row[rl(my_u, i)] = i == L ? g2 : (i == d ? gs : rl(pg, i));
-                                }
-                            }
-                        }
-                    }
-                    nF += (uint64_t)__popcll(m);
+                } else if (m && ((d == k - 2) || (d == k - 3 && sum_last)) &&
+                           flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff) <= A.flat_max) {
+                    // the next level flattened over all survivors of this chunk: the last
+                    // level, or the second-to-last with the unconstrained last level summed
+                    const bool sum_next = d == k - 3;
+                    const uint64_t passed = flat_expand(A, D, k, d, ok, v, g, pl, pg, lane, my_par, my_toff, my_tadj,
+                                                        my_gid, my_need, my_same, my_nt, my_ntf, my_u, sum_next, cnt,
+                                                        nN, nM, nS);
+                    nF += (uint64_t)__popcll(m) + (sum_next ? passed : 0);
                 } else if (m) {
                     M = m;
                     nF += (uint64_t)__popcll(m);
@@ -472,6 +531,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
         atomicAdd(&A.stats[4], (unsigned long long)nF);
         atomicAdd(&A.stats[5], (unsigned long long)t_wait);
         atomicAdd(&A.stats[6], (unsigned long long)t_busy);
+        atomicAdd(&A.stats[7], (unsigned long long)nS);
     }
 }
 
@@ -572,6 +632,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.donate_period = ctx->tune.hbm_donate_period;
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
     A.donate_last_min = ctx->tune.hbm_donate_last_min;
+    A.last_sum = ctx->tune.last_level_sum;
     k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, nq,
                                                                   total);
     HIP_TRY(hipGetLastError());
@@ -588,7 +649,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
-    unsigned long long h[7];
+    unsigned long long h[8];
     GQueue fin{};
     HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&fin, qu, sizeof(fin), hipMemcpyDeviceToHost, s));
@@ -602,6 +663,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     st->edge_checks += h[3];
     st->pushed += h[4];
     st->busy_frac = (h[5] + h[6]) ? (double)h[6] / (double)(h[5] + h[6]) : 0.0;
+    st->summed += h[7];
     {
         std::lock_guard<std::mutex> lk(ctx->ws_mu);
         ctx->last_enum = *st;  // kept even when the launch is reported as failed below

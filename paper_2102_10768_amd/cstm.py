@@ -42,6 +42,7 @@ class cstm_tune(ctypes.Structure):
         ("hbm_donate_period", ctypes.c_int32),
         ("hbm_flat_max", ctypes.c_int32),
         ("hbm_donate_last_min", ctypes.c_int32),
+        ("last_level_sum", ctypes.c_int32),
     ]
 
 
@@ -59,6 +60,7 @@ class cstm_enum_stats(ctypes.Structure):
         ("edge_checks", ctypes.c_uint64),
         ("pushed", ctypes.c_uint64),
         ("busy_frac", ctypes.c_double),
+        ("summed", ctypes.c_uint64),
     ]
 
 

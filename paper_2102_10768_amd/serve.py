@@ -6,8 +6,9 @@ Requests (query graphs) arrive one at a time.  The loop
   (each request is charged an upper bound on its CST build from the label
   index, ``Graph.estimate_bytes``, doubled for the block cache's power-of-two
   rounding; a request larger than the whole budget is refused),
-* builds each admitted request's CST on a build stream as soon as it is
-  admitted, while earlier requests are being enumerated,
+* builds each admitted request's CST as soon as it is admitted, on one of
+  several builder threads with a stream each, while earlier requests are
+  being enumerated,
 * hands every built CST to the next free enumeration lane: a lane takes all
   CSTs built so far (up to ``max_batch``) and counts them in one persistent
   launch on its own stream (``batch_count``); with two or more lanes a new
@@ -96,10 +97,10 @@ class CstmBackend:
 class Server:
     """Continuous-batching loop (see the module docstring)."""
 
-    def __init__(self, backend, *, mem_budget: int = 64 << 30, lanes: int = 2, max_batch: int = 256,
-                 clock=time.perf_counter):
-        if lanes < 1:
-            raise ValueError("lanes must be at least 1")
+    def __init__(self, backend, *, mem_budget: int = 64 << 30, lanes: int = 2, builders: int = 4,
+                 max_batch: int = 256, clock=time.perf_counter):
+        if lanes < 1 or builders < 1:
+            raise ValueError("lanes and builders must be at least 1")
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_batch = int(max_batch)
@@ -115,12 +116,13 @@ class Server:
         self._next_id = 0
         self.requests = []
         self.batches = []  # (lane, size, seconds)
-        self._threads = [threading.Thread(target=self._build_loop, name="cstm-build", daemon=True)]
+        self._build_streams = [backend.new_stream() for _ in range(builders)]
+        self._lane_streams = [backend.new_stream() for _ in range(lanes)]
+        self._threads = [threading.Thread(target=self._build_loop, args=(st,), name=f"cstm-build{i}", daemon=True)
+                         for i, st in enumerate(self._build_streams)]
         for i in range(lanes):
             self._threads.append(threading.Thread(target=self._lane_loop, args=(i,), name=f"cstm-lane{i}",
                                                   daemon=True))
-        self._build_stream = backend.new_stream()
-        self._lane_streams = [backend.new_stream() for _ in range(lanes)]
         for t in self._threads:
             t.start()
 
@@ -178,38 +180,41 @@ class Server:
             self._cv.notify_all()
         r._event.set()
 
-    def _build_loop(self):
+    def _build_loop(self, stream):
         while True:
+            refuse = None
             with self._cv:
-                while not self._pending and not self._closing:
+                while True:
+                    while not self._pending and not self._closing:
+                        self._cv.wait()
+                    if not self._pending:
+                        self._cv.notify_all()  # let the lanes see that no more work comes
+                        return
+                    r = self._pending[0]
+                    if r.charge == 0:
+                        try:
+                            r.charge = max(1, int(self.backend.estimate(r.query)))
+                        except Exception as e:  # malformed query
+                            refuse = f"rejected: {e}"
+                    if refuse is None and r.charge > self.mem_budget:
+                        refuse = f"rejected: CST bound {r.charge} B exceeds the {self.mem_budget} B budget"
+                    if refuse is not None:
+                        self._pending.popleft()
+                        r.charge = 0
+                        break
+                    # admission in arrival order: the head request waits until it fits
+                    if self._in_use + r.charge <= self.mem_budget:
+                        self._pending.popleft()
+                        self._in_use += r.charge
+                        self._peak = max(self._peak, self._in_use)
+                        r.t_admit = self.clock()
+                        break
                     self._cv.wait()
-                if not self._pending:
-                    self._cv.notify_all()  # let the lanes see that no more work comes
-                    return
-                r = self._pending[0]
-            try:
-                charge = int(self.backend.estimate(r.query))
-            except Exception as e:  # malformed query
-                with self._cv:
-                    self._pending.popleft()
-                self._finish(r, error=f"rejected: {e}")
+            if refuse is not None:
+                self._finish(r, error=refuse)
                 continue
-            if charge > self.mem_budget:
-                with self._cv:
-                    self._pending.popleft()
-                self._finish(r, error=f"rejected: CST bound {charge} B exceeds the {self.mem_budget} B budget")
-                continue
-            with self._cv:
-                # admission in arrival order: wait until the head request fits
-                while self._in_use + charge > self.mem_budget:
-                    self._cv.wait()
-                self._pending.popleft()
-                self._in_use += charge
-                self._peak = max(self._peak, self._in_use)
-                r.charge = charge
-                r.t_admit = self.clock()
             try:
-                r.handle = self.backend.build(r.query, self._build_stream)
+                r.handle = self.backend.build(r.query, stream)
             except Exception as e:
                 self._finish(r, error=f"build failed: {e}")
                 continue
