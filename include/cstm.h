@@ -84,9 +84,15 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *   deadline_ms        stop an enumeration launch after this many
  *                      milliseconds and return CSTM_ETIMEOUT, no count
  *                      reported (0 = no limit; both modes).
- *   hbm_wgs_per_cu     HBM mode: 256-thread workgroups per compute unit.
- *   hbm_donate_period  HBM mode: chunks a wavefront expands between checks
- *                      for waiting wavefronts (negative: never donate).
+ *   hbm_wgs_per_cu     HBM mode: 256-thread workgroups per compute unit
+ *                      (default 2).
+ *   hbm_donate_period  HBM mode: longest interval, in chunks of 64
+ *                      candidates, between a wavefront's checks for waiting
+ *                      wavefronts (negative: never donate; default 64).
+ *   hbm_donate_min     HBM mode: shortest such interval (default 16).  The
+ *                      interval halves back to this after a donation and
+ *                      doubles, up to hbm_donate_period, after a check that
+ *                      finds no wavefront waiting.
  *   hbm_flat_max       HBM mode: the last level is expanded as one flat list
  *                      over all surviving parents when their candidate lists
  *                      sum to at most this many entries (default 2048;
@@ -118,6 +124,7 @@ typedef struct {
     int32_t hbm_flat_max;
     int32_t hbm_donate_last_min;
     int32_t last_level_sum;
+    int32_t hbm_donate_min;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).

@@ -30,8 +30,9 @@ from . import cstm
 
 # knob -> values tried, per enumeration mode
 HBM_KNOBS = {
-    "hbm_wgs_per_cu": [2, 4, 8],
-    "hbm_donate_period": [16, 64, 256],
+    "hbm_wgs_per_cu": [2, 3, 4],
+    "hbm_donate_min": [4, 16, 32],
+    "hbm_donate_period": [64, 256],
     "hbm_flat_max": [-1, 2048, 16384],
     "hbm_donate_last_min": [1024, 4096, 65536],
 }

@@ -194,11 +194,12 @@ static void apply_defaults(cstm_ctx* c) {
     if (t.max_replication == 0) t.max_replication = 16;  // negative: no limit
     if (t.enum_mode < CSTM_MODE_AUTO || t.enum_mode > CSTM_MODE_HBM) t.enum_mode = CSTM_MODE_AUTO;
     if (t.deadline_ms < 0) t.deadline_ms = 0;
-    if (t.hbm_wgs_per_cu <= 0) t.hbm_wgs_per_cu = 4;
+    if (t.hbm_wgs_per_cu <= 0) t.hbm_wgs_per_cu = 2;
     if (t.hbm_donate_period == 0) t.hbm_donate_period = 64;
     if (t.hbm_flat_max == 0) t.hbm_flat_max = 2048;
     if (t.hbm_donate_last_min <= 0) t.hbm_donate_last_min = 4096;
     if (t.last_level_sum == 0) t.last_level_sum = 1;
+    if (t.hbm_donate_min <= 0) t.hbm_donate_min = 16;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,

@@ -63,13 +63,15 @@ struct GArgs {
     unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks, summed] or nullptr
     uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave may wait
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
-    int donate_period;          // chunks between donation checks (<= 0: never)
+    int donate_period;          // longest interval in chunks between donation checks (<= 0: never donate)
+    int donate_min;             // shortest such interval
     int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
     int64_t donate_last_min;    // smallest last-level remainder worth donating
     int last_sum;               // > 0: count an unconstrained last level by list lengths
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
+
 
 __device__ inline int mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -323,6 +325,10 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const CstDev* D = nullptr;
     uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
+    // chunks between checks for waiting consumers, adapted per wavefront
+    const uint32_t max_period = (uint32_t)(A.donate_period > 0 ? A.donate_period : 64);
+    const uint32_t min_period = (uint32_t)A.donate_min < max_period ? (uint32_t)A.donate_min : max_period;
+    uint32_t period = A.donate_period > 0 ? min_period : max_period;
     for (;;) {
         const uint64_t w0 = now_ticks();
         const long long slot = pop_task(A, lane);
@@ -455,8 +461,10 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                     nF += (uint64_t)__popcll(m);
                 }
                 // every few chunks: stop on abort or deadline; donate the untouched
-                // remainder of the shallowest open level when a consumer is waiting
-                if (++since_check >= (uint32_t)(A.donate_period > 0 ? A.donate_period : 64)) {
+                // remainder of the shallowest open level when a consumer is waiting.
+                // The interval adapts: short while consumers wait (a narrow search
+                // spreads fast), doubling up to donate_period while none do.
+                if (++since_check >= period) {
                     since_check = 0;
                     int want = 0;
                     if (lane == 0) {
@@ -471,17 +479,21 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                     }
                     want = __shfl(want, 0);
                     if (want < 0) break;
+                    if (!want) period = period * 2 < max_period ? period * 2 : max_period;
                     if (want) {
                         // shallowest open level first: its untouched list remainder, or
                         // (above the current level) the survivors not yet descended into,
                         // given away as a range the receiver re-checks
+                        // the last level visited holds cheap entries: only large remainders go
+                        const int last_visited = sum_last ? k - 2 : k - 1;
                         for (int dd = j; dd <= d; ++dd) {
                             const int64_t c2 = rl(lc, dd), e2 = rl(le, dd);
-                            if (dd == k - 1 && e2 - c2 < A.donate_last_min) break;
+                            if (dd == last_visited && e2 - c2 < A.donate_last_min) break;
                             if (c2 < e2) {
                                 if (push_task(A, q, dd, c2, e2, pl, lane)) {
                                     le = setl(le, c2, lane, dd);
                                     ++ndon;
+                                    period = min_period;
                                 }
                                 break;
                             }
@@ -493,6 +505,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                                 if (from < to && push_task(A, q, dd, from, to, pl, lane)) {
                                     lm = setl(lm, (uint64_t)0, lane, dd);
                                     ++ndon;
+                                    period = min_period;
                                 }
                                 break;
                             }
@@ -630,6 +643,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
     A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
     A.donate_period = ctx->tune.hbm_donate_period;
+    A.donate_min = ctx->tune.hbm_donate_min > 0 ? ctx->tune.hbm_donate_min : 1;
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
     A.donate_last_min = ctx->tune.hbm_donate_last_min;
     A.last_sum = ctx->tune.last_level_sum;

@@ -43,6 +43,7 @@ class cstm_tune(ctypes.Structure):
         ("hbm_flat_max", ctypes.c_int32),
         ("hbm_donate_last_min", ctypes.c_int32),
         ("last_level_sum", ctypes.c_int32),
+        ("hbm_donate_min", ctypes.c_int32),
     ]
 
 
