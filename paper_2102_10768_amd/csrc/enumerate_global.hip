@@ -232,78 +232,108 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
     // with sum_next: where the last level's list owner sits
     const int pK = sum_next ? rl(my_par, L + 1) : 0;
     const int64_t* toffK = sum_next ? (const int64_t*)rlp(my_toff, L + 1) : nullptr;
-    int64_t b0 = 0, len = 0;
+    int64_t b0 = 0;
+    int32_t len = 0;  // the caller checked that the lengths sum to at most flat_max < 2^31
     if (ok) {
         const int32_t x = pk == d ? v : rl(pl, pk);
         b0 = toffL[x];
-        len = toffL[x + 1] - b0;
+        len = (int32_t)(toffL[x + 1] - b0);
     }
-    int64_t incl = len;  // inclusive prefix over lanes
+    int32_t incl = len;  // inclusive prefix over lanes
     for (int o = 1; o < CSTM_WAVE; o <<= 1) {
-        const int64_t y = __shfl_up(incl, o, CSTM_WAVE);
+        const int32_t y = __shfl_up(incl, o, CSTM_WAVE);
         if (lane >= o) incl += y;
     }
-    const int64_t total = __shfl(incl, CSTM_WAVE - 1);
+    const int32_t total = __shfl(incl, CSTM_WAVE - 1);
     uint64_t passed = 0;
-    for (int64_t t0 = 0; t0 < total; t0 += CSTM_WAVE) {
-        const int64_t t = t0 + lane;
-        const bool val2 = t < total;
-        // owner lane: first lane whose inclusive prefix exceeds t
-        int lo2 = 0, hi2 = CSTM_WAVE - 1;
-        while (lo2 < hi2) {
-            const int mid = (lo2 + hi2) >> 1;
-            if (__shfl(incl, mid) > t) hi2 = mid;
-            else lo2 = mid + 1;
+    // Two rounds of 64 pairs per iteration: their owner searches and loads are
+    // independent, so each hides the other's latency.
+    constexpr int R = 2;
+    for (int32_t t0 = 0; t0 < total; t0 += R * CSTM_WAVE) {
+        int32_t t[R], lo2[R], hi2[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            t[r] = t0 + r * CSTM_WAVE + lane;
+            lo2[r] = 0;
+            hi2[r] = CSTM_WAVE - 1;
         }
-        const int sl = lo2;
-        const int64_t start = __shfl(incl, sl) - __shfl(len, sl);
-        const int64_t bs = __shfl(b0, sl);
-        const int32_t vs = __shfl(v, sl), gs = __shfl(g, sl);
-        int32_t v2 = 0;
-        if (val2) v2 = tadjL[bs + (t - start)];
-        const int32_t g2 = (val2 && needL) ? gidL[v2] : -1;
-        bool ok2 = val2;
-        uint32_t same2 = sameL;
-        while (same2) {
-            const int jj = __ffs(same2) - 1;
-            same2 &= same2 - 1;
-            ok2 = ok2 && g2 != (jj == d ? gs : rl(pg, jj));
+        // owner lane of pair t: first lane whose inclusive prefix exceeds t
+#pragma unroll
+        for (int it = 0; it < 6; ++it) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int mid = (lo2[r] + hi2[r]) >> 1;
+                if (__shfl(incl, mid) > t[r]) hi2[r] = mid;
+                else lo2[r] = mid + 1;
+            }
         }
-        uint32_t nt2 = ntL, e2 = ntfL;
-        while (nt2) {
-            const int jj = __ffs(nt2) - 1;
-            nt2 &= nt2 - 1;
-            const NtDesc& N = D->nt[e2++];
-            const int32_t x = jj == d ? vs : rl(pl, jj);
-            if (ok2) ok2 = contains(N.adj_gid, N.off[x], N.off[x + 1], g2);
+        bool val2[R], ok2[R];
+        int32_t v2[R], g2[R], vs[R], gs[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int sl = lo2[r];
+            val2[r] = t[r] < total;
+            const int32_t start = __shfl(incl, sl) - __shfl(len, sl);
+            const int64_t bs = __shfl(b0, sl);
+            vs[r] = __shfl(v, sl);
+            gs[r] = __shfl(g, sl);
+            v2[r] = val2[r] ? tadjL[bs + (t[r] - start)] : 0;
         }
-        const uint64_t m2 = __ballot(ok2);
-        const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2));
-        nN += nv2;
-        nM += nv2 * (uint64_t)__popc(ntL);
-        passed += (uint64_t)__popcll(m2);
+#pragma unroll
+        for (int r = 0; r < R; ++r) g2[r] = (val2[r] && needL) ? gidL[v2[r]] : -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bool okr = val2[r];
+            uint32_t same2 = sameL;
+            while (same2) {
+                const int jj = __ffs(same2) - 1;
+                same2 &= same2 - 1;
+                okr = okr && g2[r] != (jj == d ? gs[r] : rl(pg, jj));
+            }
+            uint32_t nt2 = ntL, e2 = ntfL;
+            while (nt2) {
+                const int jj = __ffs(nt2) - 1;
+                nt2 &= nt2 - 1;
+                const NtDesc& N = D->nt[e2++];
+                const int32_t x = jj == d ? vs[r] : rl(pl, jj);
+                if (okr) okr = contains(N.adj_gid, N.off[x], N.off[x + 1], g2[r]);
+            }
+            ok2[r] = okr;
+        }
         if (sum_next) {
             int64_t lk = 0;
-            if (ok2) {
-                const int32_t xk = pK == L ? v2 : (pK == d ? vs : rl(pl, pK));
-                lk = toffK[xk + 1] - toffK[xk];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ok2[r]) {
+                    const int32_t xk = pK == L ? v2[r] : (pK == d ? vs[r] : rl(pl, pK));
+                    lk += toffK[xk + 1] - toffK[xk];
+                }
             }
             for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) lk += __shfl_xor(lk, o, CSTM_WAVE);
             cnt += (uint64_t)lk;
             nN += (uint64_t)lk;
             nS += (uint64_t)lk;
-            continue;
         }
-        cnt += (uint64_t)__popcll(m2);
-        if (A.list && m2) {
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m2));
-            base = __shfl(base, 0);
-            if (ok2) {
-                const uint64_t r = base + (uint64_t)mbcnt(m2);
-                if (r < A.cap) {
-                    int32_t* row = A.rows + r * (uint64_t)k;
-                    for (int i = 0; i < k; ++i) row[rl(my_u, i)] = i == L ? g2 : (i == d ? gs : rl(pg, i));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t m2 = __ballot(ok2[r]);
+            const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2[r]));
+            nN += nv2;
+            nM += nv2 * (uint64_t)__popc(ntL);
+            passed += (uint64_t)__popcll(m2);
+            if (sum_next) continue;
+            cnt += (uint64_t)__popcll(m2);
+            if (A.list && m2) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(A.row_cursor, (unsigned long long)__popcll(m2));
+                base = __shfl(base, 0);
+                if (ok2[r]) {
+                    const uint64_t row_i = base + (uint64_t)mbcnt(m2);
+                    if (row_i < A.cap) {
+                        int32_t* row = A.rows + row_i * (uint64_t)k;
+                        for (int i = 0; i < k; ++i)
+                            row[rl(my_u, i)] = i == L ? g2[r] : (i == d ? gs[r] : rl(pg, i));
+                    }
                 }
             }
         }
