@@ -132,41 +132,61 @@ def erdos_renyi(n: int, p: float, seed: int):
     return csr_from_edges(n, i, j)
 
 
-def chung_lu(n: int, m_target: int, gamma: float, seed: int):
+def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
     """Chung-Lu power-law graph, uncapped weights w_i ~ (i+1)^(-1/(gamma-1)).
 
     Both endpoints of an edge are drawn independently with probability
     proportional to their weight.  Draws continue until ``m_target`` distinct
     non-loop pairs were seen; the first ``m_target`` distinct pairs in draw order
     are kept.  Vertex ids are then shuffled so that id and degree are unrelated.
+    Uniforms are drawn in chunks (the same stream as one draw per batch), so
+    large graphs need little temporary memory; ``log`` receives progress lines.
     """
     rng = _rng(seed, STREAM_EDGES)
     w = np.power(np.arange(1, n + 1, dtype=np.float64), -1.0 / (gamma - 1.0))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
+    del w
+    chunk = 1 << 24
+    itype = np.int32 if n < (1 << 31) else np.int64
+
+    def endpoints(count):
+        out = np.empty(count, dtype=itype)
+        for s0 in range(0, count, chunk):
+            s1 = min(count, s0 + chunk)
+            out[s0:s1] = np.minimum(np.searchsorted(cdf, rng.random(s1 - s0), side="right"), n - 1)
+        return out
+
     all_keys = np.zeros(0, dtype=np.int64)
     while True:
         need = m_target - all_keys.shape[0]
         batch = int(need * 1.3) + 4096
-        a = np.searchsorted(cdf, rng.random(batch), side="right")
-        b = np.searchsorted(cdf, rng.random(batch), side="right")
-        a = np.minimum(a, n - 1).astype(np.int64)
-        b = np.minimum(b, n - 1).astype(np.int64)
+        a = endpoints(batch)
+        b = endpoints(batch)
         keep = a != b
-        lo = np.minimum(a[keep], b[keep])
-        hi = np.maximum(a[keep], b[keep])
-        all_keys = np.concatenate([all_keys, lo * n + hi])
+        a, b = a[keep].astype(np.int64), b[keep].astype(np.int64)
+        key = np.minimum(a, b) * n + np.maximum(a, b)
+        del a, b, keep
+        all_keys = np.concatenate([all_keys, key])
+        del key
         # keep the distinct pairs in the order they were first drawn
         _, first = np.unique(all_keys, return_index=True)
         first.sort()
+        if log:
+            log(f"chung_lu: {all_keys.shape[0]} pairs drawn, {first.shape[0]} distinct of {m_target}")
         if first.shape[0] >= m_target:
             all_keys = all_keys[first[:m_target]]
             break
         all_keys = all_keys[first]
+        del first
     lo = all_keys // n
     hi = all_keys % n
+    del all_keys
     perm = _rng(seed, STREAM_PERM).permutation(n).astype(np.int64)
-    return csr_from_edges(n, perm[lo], perm[hi])
+    out = csr_from_edges(n, perm[lo], perm[hi])
+    if log:
+        log("chung_lu: CSR built")
+    return out
 
 
 def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int, chunk: int = 1 << 24):
@@ -216,7 +236,7 @@ def zipf_labels(n: int, num_labels: int, s: float, seed: int) -> np.ndarray:
     return rng.choice(num_labels, size=n, p=p).astype(np.int32)
 
 
-def make_graph(spec: dict) -> Graph:
+def make_graph(spec: dict, log=None) -> Graph:
     """Build a graph from a plain dict spec.
 
     ``{"kind": "er", "n", "p"}``, ``{"kind": "chung_lu", "n", "m", "gamma"}`` or
@@ -230,7 +250,7 @@ def make_graph(spec: dict) -> Graph:
         row_ptr, col = erdos_renyi(n, float(spec["p"]), seed)
     elif kind == "chung_lu":
         n = int(spec["n"])
-        row_ptr, col = chung_lu(n, int(spec["m"]), float(spec["gamma"]), seed)
+        row_ptr, col = chung_lu(n, int(spec["m"]), float(spec["gamma"]), seed, log=log)
     elif kind == "rmat":
         n = 1 << int(spec["scale"])
         row_ptr, col = rmat(

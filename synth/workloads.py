@@ -34,4 +34,15 @@ RMAT_22 = {
     "queries": {"k_min": 4, "k_max": 16, "count": 1000, "seed": 23},
 }
 
-ALL = {w["name"]: w for w in (SMALL, POWER_LAW_1M, RMAT_22)}
+SERVE_16M = {
+    "name": "c4",
+    "title": "Chung-Lu 16M vertices, 256M edges, gamma 2.1, 100 Zipf(0.8) labels; "
+             "screened pool of random-walk queries of 4..24 vertices, Poisson arrivals",
+    "graph": {"kind": "chung_lu", "n": 16_000_000, "m": 256_000_000, "gamma": 2.1, "seed": 14,
+              "labels": {"kind": "zipf", "L": 100, "s": 0.8}},
+    "queries": {"k_min": 4, "k_max": 24, "count": 200, "seed": 24},
+    # request streams: 2,000 arrivals per rate, one seed per rate; admission budget
+    "serve": {"rates": [50, 200, 800], "arrivals": 2000, "seeds": [201, 202, 203], "mem_budget_gb": 64},
+}
+
+ALL = {w["name"]: w for w in (SMALL, POWER_LAW_1M, RMAT_22, SERVE_16M)}

@@ -58,7 +58,7 @@ def _check_rows(g, q, rows):
             assert g.has_edge(int(r[a]), int(r[b]))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_stored_counts_plain_form(name):
     from paper_2102_10768_amd import cstm
 
@@ -72,7 +72,7 @@ def test_stored_counts_plain_form(name):
         c.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_stored_counts_batched_form(name):
     from paper_2102_10768_amd import cstm
 
@@ -86,7 +86,7 @@ def test_stored_counts_batched_form(name):
     assert got == [d["count"] for d in W["queries"]]
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_sampled_rows_are_embeddings(name):
     from paper_2102_10768_amd import cstm
 
@@ -147,7 +147,7 @@ def test_deadline_stops_a_launch_and_the_context_recovers():
     c2.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_footprint_estimate_bounds_the_built_cst(name):
     """The label-index estimate never falls below the CST bytes actually built."""
     from paper_2102_10768_amd import cstm
