@@ -34,17 +34,54 @@ __device__ inline int mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
+// Rows of a candidate array laid end to end: entry t of the flattened space is
+// entry t - rowoff[i] of the CSR row of candidate i, where rowoff is the
+// exclusive prefix sum of the candidates' degrees.  Kernels walk this space in
+// tiles of kTile entries, one wavefront per tile, so a hub's long row is shared
+// by many wavefronts and short rows are packed together.
+constexpr int kTile = 512;
+
+struct Rows {
+    const int32_t* cand;    // candidate data-vertex ids
+    const int64_t* rowoff;  // n + 1 prefix sums of their degrees
+    int64_t n;
+    int64_t total;          // rowoff[n]
+};
+
+// The candidate whose row holds flattened entry t: the last i in [lo, hi]
+// with rowoff[i] <= t (empty rows are skipped by construction).
+__device__ inline int64_t owner_of(const int64_t* __restrict__ rowoff, int64_t lo, int64_t hi, int64_t t) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rowoff[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_cand_degrees(const int32_t* __restrict__ cand, int64_t n, const int64_t* __restrict__ row_ptr,
+                               int64_t* __restrict__ deg) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t v = cand[i];
+        deg[i] = row_ptr[v + 1] - row_ptr[v];
+    }
+}
+
 // Top-down marking: every neighbour of a parent candidate that passes u's
 // label/degree filter is marked in u's rank table.
-__global__ void k_mark(const int32_t* __restrict__ pc, int64_t np, const int64_t* __restrict__ row_ptr,
-                       const int32_t* __restrict__ col, const uint64_t* __restrict__ lab_rank, uint64_t key,
-                       int64_t cnt0, int32_t* __restrict__ mark) {
+__global__ void k_mark(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                       const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0, int32_t* __restrict__ mark) {
     const int lane = lane_id();
-    for (int64_t i = global_wave(); i < np; i += num_waves()) {
-        int32_t v = pc[i];
-        int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        for (int64_t j = b + lane; j < e; j += CSTM_WAVE) {
-            uint64_t d = lab_rank[col[j]] - key;
+    const int64_t ntiles = (R.total + kTile - 1) / kTile;
+    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
+        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
+        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
+        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
+        for (int64_t t = t0 + lane; t < t1; t += CSTM_WAVE) {
+            const int64_t i = owner_of(R.rowoff, lo, hi, t);
+            const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
+            const uint64_t d = lab_rank[col[j]] - key;
             if (d < (uint64_t)cnt0) mark[d] = 1;
         }
     }
@@ -128,51 +165,89 @@ __global__ void k_refine(const int32_t* __restrict__ cand_old, const int32_t* __
     }
 }
 
-// List sizes: |N_G(v) ∩ C(u')| per candidate v of the list's owner.
-__global__ void k_list_count(const int32_t* __restrict__ pc, int64_t np, const int64_t* __restrict__ row_ptr,
-                             const int32_t* __restrict__ col, const uint64_t* __restrict__ lab_rank, uint64_t key,
-                             int64_t cnt0, const int32_t* __restrict__ loc, int64_t* __restrict__ cnt,
-                             int* __restrict__ max_len) {
+// List sizes: |N_G(v) ∩ C(u')| per candidate v of the list's owner, added to
+// cnt (zeroed by the caller) once per run of lanes with the same owner; the
+// number of list entries in each tile goes to tile_cnt.
+__global__ void k_list_count(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0,
+                             const int32_t* __restrict__ loc, unsigned long long* __restrict__ cnt,
+                             int64_t* __restrict__ tile_cnt) {
     const int lane = lane_id();
-    int local_max = 0;
-    for (int64_t i = global_wave(); i < np; i += num_waves()) {
-        int32_t v = pc[i];
-        int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        int64_t c = 0;
-        for (int64_t j0 = b; j0 < e; j0 += CSTM_WAVE) {
-            int64_t j = j0 + lane;
+    const int64_t ntiles = (R.total + kTile - 1) / kTile;
+    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
+        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
+        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
+        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
+        int64_t in_tile = 0;
+        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
+            const int64_t t = s0 + lane;
+            const bool in = t < t1;
+            const int64_t i = in ? owner_of(R.rowoff, lo, hi, t) : hi;
             bool hit = false;
-            if (j < e) {
-                uint64_t d = lab_rank[col[j]] - key;
+            if (in) {
+                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
+                const uint64_t d = lab_rank[col[j]] - key;
                 hit = d < (uint64_t)cnt0 && loc[d] >= 0;
             }
-            c += __popcll(ballot(hit));
+            const uint64_t hits = ballot(hit);
+            in_tile += __popcll(hits);
+            // owners never decrease across lanes: one atomic per run of equal owners
+            const int64_t prev = __shfl_up(i, 1, CSTM_WAVE);
+            const bool head = lane == 0 || prev != i;
+            const uint64_t heads = ballot(head);
+            if (head) {
+                const uint64_t later = lane == CSTM_WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+                const uint64_t upto = later ? (later & (~later + 1)) - 1 : ~0ull;  // bits below the next head
+                const uint64_t run = upto & ~((1ull << lane) - 1);
+                const int c = __popcll(hits & run);
+                if (c) atomicAdd(&cnt[i], (unsigned long long)c);
+            }
         }
-        if (lane == 0) cnt[i] = c;
-        local_max = c > local_max ? (int)c : local_max;
+        if (lane == 0) tile_cnt[tile] = in_tile;
     }
-    if (lane == 0 && local_max) atomicMax(max_len, local_max);
 }
 
-// List entries, in G's row order (ascending data-vertex id), as indices into C(u').
-__global__ void k_list_fill(const int32_t* __restrict__ pc, int64_t np, const int64_t* __restrict__ row_ptr,
-                            const int32_t* __restrict__ col, const uint64_t* __restrict__ lab_rank, uint64_t key,
-                            int64_t cnt0, const int32_t* __restrict__ loc, const int64_t* __restrict__ off,
+// Largest list length, from the list offsets.
+__global__ void k_max_len(const int64_t* __restrict__ off, int64_t n, int* __restrict__ max_len) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t len = off[i + 1] - off[i];
+        m = len > m ? (int)len : m;
+    }
+    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) {
+        const int y = __shfl_xor(m, o, CSTM_WAVE);
+        m = y > m ? y : m;
+    }
+    if (lane_id() == 0 && m) atomicMax(max_len, m);
+}
+
+// List entries, in G's row order (ascending data-vertex id), as indices into
+// C(u'): the hits of the flattened space are numbered in order, tile by tile
+// from tile_base, which lays the lists of consecutive owners end to end exactly
+// as the offsets from the per-owner counts do.
+__global__ void k_list_fill(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0,
+                            const int32_t* __restrict__ loc, const int64_t* __restrict__ tile_base,
                             int32_t* __restrict__ adj, int32_t* __restrict__ adj_gid) {
     const int lane = lane_id();
-    for (int64_t i = global_wave(); i < np; i += num_waves()) {
-        int32_t v = pc[i];
-        int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        int64_t out = off[i];
-        for (int64_t j0 = b; j0 < e; j0 += CSTM_WAVE) {
-            int64_t j = j0 + lane;
+    const int64_t ntiles = (R.total + kTile - 1) / kTile;
+    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
+        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
+        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
+        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
+        int64_t out = tile_base[tile];
+        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
+            const int64_t t = s0 + lane;
             int32_t idx = -1, w = 0;
-            if (j < e) {
+            if (t < t1) {
+                const int64_t i = owner_of(R.rowoff, lo, hi, t);
+                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
                 w = col[j];
-                uint64_t d = lab_rank[w] - key;
+                const uint64_t d = lab_rank[w] - key;
                 if (d < (uint64_t)cnt0) idx = loc[d];
             }
-            uint64_t m = ballot(idx >= 0);
+            const uint64_t m = ballot(idx >= 0);
             if (idx >= 0) {
                 adj[out + mbcnt(m)] = idx;
                 if (adj_gid) adj_gid[out + mbcnt(m)] = w;
@@ -289,30 +364,66 @@ struct EventTimer {
 
 }  // namespace
 
+// Flattened rows of n candidates: degrees, then their prefix sums into rowoff
+// (n + 1 entries).  Returns the total number of row entries.
+static Rows flat_rows(cstm_cst* c, const int32_t* cand, int64_t n, int64_t* deg, int64_t* rowoff) {
+    hipStream_t s = c->stream;
+    if (n) {
+        k_cand_degrees<<<cstm_blocks(n, 256, 4096), 256, 0, s>>>(cand, n, c->g->row_ptr, deg);
+        HIP_TRY(hipGetLastError());
+    }
+    Rows R;
+    R.cand = cand;
+    R.rowoff = rowoff;
+    R.n = n;
+    R.total = cstm_exclusive_scan_i64(c->ctx, deg, rowoff, n, s);
+    return R;
+}
+
+static unsigned tile_grid(int64_t total) {
+    const int64_t tiles = (total + kTile - 1) / kTile;
+    return wave_grid(tiles > 0 ? tiles : 1);
+}
+
 // The lists of `from` (a query vertex) into `to`, using to's rank table.
+// Scratch: deg, rowoff and cnt hold at least #C(from) + 1 int64 entries.
 static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, EdgeLists& el, int* d_max,
-                        int64_t* d_cnt, bool with_gid) {
+                        int64_t* deg, int64_t* rowoff, int64_t* cnt, bool with_gid) {
     const cstm_graph* g = c->g;
     hipStream_t s = c->stream;
     const int64_t np = c->ncand[from];
     uint64_t key = (uint64_t)c->qlabel[to] << 32;
     el.off = c->mem.get_n<int64_t>(np + 1);
     HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int), s));
-    if (np) {
-        k_list_count<<<wave_grid(np), kWaveBlock, 0, s>>>(c->cand[from], np, g->row_ptr, g->col, g->lab_rank, key,
-                                                          c->cnt0[to], loc[to], d_cnt, d_max);
+    const Rows R = flat_rows(c, c->cand[from], np, deg, rowoff);
+    const int64_t ntiles = (R.total + kTile - 1) / kTile;
+    int64_t* tile_cnt = c->mem.get_n<int64_t>(ntiles + 1);
+    if (np) HIP_TRY(hipMemsetAsync(cnt, 0, (size_t)np * sizeof(int64_t), s));
+    if (ntiles) {
+        k_list_count<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank, key, c->cnt0[to],
+                                                               loc[to], (unsigned long long*)cnt, tile_cnt);
         HIP_TRY(hipGetLastError());
     }
-    el.entries = cstm_exclusive_scan_i64(c->ctx, d_cnt, el.off, np, s);
+    el.entries = cstm_exclusive_scan_i64(c->ctx, cnt, el.off, np, s);
+    if (np) {
+        k_max_len<<<cstm_blocks(np, 256, 1024), 256, 0, s>>>(el.off, np, d_max);
+        HIP_TRY(hipGetLastError());
+    }
     el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
     if (with_gid) el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-    if (np && el.entries) {
-        k_list_fill<<<wave_grid(np), kWaveBlock, 0, s>>>(c->cand[from], np, g->row_ptr, g->col, g->lab_rank, key,
-                                                         c->cnt0[to], loc[to], el.off, el.adj, el.adj_gid);
+    if (ntiles && el.entries) {
+        int64_t* tile_base = c->mem.get_n<int64_t>(ntiles + 1);
+        const int64_t again = cstm_exclusive_scan_i64(c->ctx, tile_cnt, tile_base, ntiles, s);
+        CSTM_REQUIRE(again == el.entries, CSTM_EDEVICE, "candidate list counts disagree");
+        k_list_fill<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank, key, c->cnt0[to],
+                                                              loc[to], tile_base, el.adj, el.adj_gid);
         HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        c->mem.release(tile_base);
     }
     HIP_TRY(hipMemcpyAsync(&el.max_len, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    c->mem.release(tile_cnt);
 }
 
 static void build_cst(cstm_cst* c, const QueryPrep& q) {
@@ -363,6 +474,8 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         for (int u = 0; u < k; ++u) max_cnt0 = std::max(max_cnt0, c->cnt0[u]);
         int32_t* scan = c->mem.get_n<int32_t>(max_cnt0 + 1);
         int32_t* flag = c->mem.get_n<int32_t>(max_cnt0 + 1);
+        int64_t* fdeg = c->mem.get_n<int64_t>(max_cnt0 + 1);
+        int64_t* frow = c->mem.get_n<int64_t>(max_cnt0 + 1);
         // 1. root candidates: the filtered prefix of the root's label group
         loc[root] = c->mem.get_n<int32_t>(c->cnt0[root]);
         c->cand[root] = c->mem.get_n<int32_t>(c->cnt0[root]);
@@ -375,10 +488,12 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             int u = c->bfs[t], up = c->parent[u];
             loc[u] = c->mem.get_n<int32_t>(c->cnt0[u]);
             HIP_TRY(hipMemsetAsync(loc[u], 0, c->cnt0[u] * sizeof(int32_t), s));
-            k_mark<<<wave_grid(c->ncand[up]), kWaveBlock, 0, s>>>(c->cand[up], c->ncand[up], g->row_ptr, g->col,
-                                                                   g->lab_rank, (uint64_t)q.qlabel[u] << 32,
-                                                                   c->cnt0[u], loc[u]);
-            HIP_TRY(hipGetLastError());
+            const Rows R = flat_rows(c, c->cand[up], c->ncand[up], fdeg, frow);
+            if (R.total) {
+                k_mark<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank,
+                                                                 (uint64_t)q.qlabel[u] << 32, c->cnt0[u], loc[u]);
+                HIP_TRY(hipGetLastError());
+            }
             int64_t nu = cstm_exclusive_scan_i32(c->ctx, loc[u], scan, c->cnt0[u], s);
             c->ncand[u] = nu;
             c->cand[u] = c->mem.get_n<int32_t>(nu ? nu : 1);
@@ -418,6 +533,8 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         }
         c->mem.release(flag);
         c->mem.release(scan);
+        c->mem.release(fdeg);
+        c->mem.release(frow);
     }
 
     // 4a. tree lists
@@ -425,10 +542,12 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     int64_t maxn = 1;
     for (int u = 0; u < k; ++u) maxn = std::max(maxn, c->ncand[u]);
     int64_t* d_cnt = c->mem.get_n<int64_t>(maxn + 1);
+    int64_t* l_deg = c->mem.get_n<int64_t>(maxn + 1);
+    int64_t* l_row = c->mem.get_n<int64_t>(maxn + 1);
     if (!c->empty) {
         for (int t = 1; t < k; ++t) {
             int u = c->bfs[t];
-            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max, d_cnt, false);
+            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max, l_deg, l_row, d_cnt, false);
             c->d_cst = std::max(c->d_cst, c->tree[u].max_len);
         }
     }
@@ -490,7 +609,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.from = c->pos_of[a];
         el.to = c->pos_of[b];
         if (!c->empty) {
-            build_lists(c, a, b, loc, el, d_max, d_cnt, true);
+            build_lists(c, a, b, loc, el, d_max, l_deg, l_row, d_cnt, true);
             c->d_cst = std::max(c->d_cst, el.max_len);
         } else {
             el.off = nullptr;
@@ -504,6 +623,8 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     for (int u = 0; u < k; ++u)
         if (loc[u]) c->mem.release(loc[u]);
     c->mem.release(d_cnt);
+    c->mem.release(l_deg);
+    c->mem.release(l_row);
     c->mem.release(d_max);
 
     // descriptor in order positions
