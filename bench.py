@@ -307,11 +307,13 @@ def serve_main(a, W, g, queries, expected):
         picks = np.random.Generator(np.random.PCG64(301 + i)).integers(0, len(queries), size=n)
         qs = [queries[int(p)] for p in picks]
         want = [expected[int(p)] for p in picks]
-        with serve.Server(backend, mem_budget=budget, lanes=2, builders=4) as srv:
-            served = serve.replay(srv, arr, qs)
+        with cstm.Server(ctx, G, mem_budget=budget, lanes=2, builders=4) as srv:
+            served = serve.replay_native(srv, arr, qs)
+            sst = srv.stats()
         s_srv = serve.summarize(served)
-        s_srv["peak_charged_bytes"] = srv.peak_bytes
-        s_srv["lane_overlap"] = srv.max_overlap
+        s_srv["peak_charged_bytes"] = sst["peak_bytes"]
+        s_srv["lane_overlap"] = sst["max_overlap"]
+        s_srv["launches"] = sst["launches"]
         print(f"{qps} QPS served: {s_srv}", file=sys.stderr, flush=True)
         plain = serve.run_sequential(backend, arr, qs)
         s_pl = serve.summarize(plain)
@@ -338,8 +340,8 @@ def serve_main(a, W, g, queries, expected):
         "config": {
             "workload": W["workload"]["title"],
             "name": a.workload,
-            "form": "served: Poisson arrivals, admission by CST footprint bound, 4 CST builders, "
-                    "2 enumeration lanes with batched persistent launches; value is at the highest rate",
+            "form": "served (cstm_server): Poisson arrivals, admission by CST footprint bound, 4 CST builder "
+                    "threads, 2 enumeration lanes with batched persistent launches; value is at the highest rate",
             "query_pool": len(queries),
             "mem_budget_bytes": budget,
         },

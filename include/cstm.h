@@ -229,19 +229,81 @@ cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
  * memory: cap entries at most; *n_out receives #C(u). */
 cstm_status cstm_cst_candidates(const cstm_cst* cst, int32_t u, int32_t* out, int64_t cap, int64_t* n_out);
 
-/* Enumerate the embeddings of a partitioned CST (partitions it first with the
- * context's tuning if it is not).  list = 0 counts only; list = 1 also writes
- * rows to the DEVICE buffer rows[cap][k] (row[u] = data vertex of query vertex
- * u, rows in no particular order).  *count_out receives the exact number of
- * embeddings; *rows_written min(count, cap).  Returns CSTM_EOVERFLOW when
- * list = 1 and count > cap. */
-cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap, uint64_t* count_out,
-                           uint64_t* rows_written, void* stream);
+/* Enumerate the embeddings of one CST (Section VI-A; where the CST is read
+ * from follows tune.enum_mode: partitions the caller made with
+ * cstm_cst_partition are staged into LDS, otherwise the CST is read from
+ * device memory).  list = 0 counts only; list = 1 also writes rows to the
+ * DEVICE buffer rows[cap][k] (row[u] = data vertex of query vertex u, rows in
+ * no particular order).
+ *   limit        0: find every embedding.  > 0: stop early once at least
+ *                limit embeddings were found; *count_out is then exactly
+ *                min(total, limit), whatever order the search ran in.
+ *   deadline_s   > 0: stop the launch after this many seconds and return
+ *                CSTM_ETIMEOUT (nothing is reported); <= 0: the context's
+ *                tune.deadline_ms applies.
+ * *count_out receives the exact number of embeddings (or min(total, limit));
+ * *rows_written min(that, cap).  Returns CSTM_EOVERFLOW when list = 1 and the
+ * number exceeds cap (the count is still exact). */
+cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* rows, uint64_t cap,
+                           uint64_t* count_out, uint64_t* rows_written, double deadline_s, void* stream);
 
 /* Enumerate (count) many partitioned CSTs in one persistent launch that draws
  * partitions from a device work queue.  counts_out[nq] is a host array. */
 cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
                                  void* stream);
+
+/* ---------------------------------------------------------------- serving
+ *
+ * A request loop over one resident graph (the serving form of the method:
+ * queries arrive one at a time and share the GPU).  The server admits
+ * requests in arrival order while the device-memory bound of their CSTs
+ * (cstm_cst_estimate, doubled for the block cache's rounding) fits
+ * mem_budget; builds admitted CSTs on `builders` threads, each with its own
+ * stream; and gives every built CST to the next free enumeration lane, which
+ * counts all CSTs built so far (up to max_batch) in one persistent launch on
+ * its own stream.  Several lanes run launches at the same time.  A request's
+ * count does not depend on which requests share its launch.  The server is
+ * thread-safe; it uses the context's tuning (deadline_ms applies per launch).
+ * Zero or negative lanes / builders / max_batch take the defaults 2 / 4 / 256.
+ * Errors: CSTM_EINVAL for NULL arguments or a graph of another context. */
+typedef struct cstm_server cstm_server;
+typedef struct {
+    int32_t done;        /* 1: finished; the fields below are set                   */
+    int32_t status;      /* the request's outcome: CSTM_OK; CSTM_ENOMEM when its CST
+                            bound exceeds the whole budget; CSTM_EINVAL for a
+                            malformed query; CSTM_ETIMEOUT / CSTM_EDEVICE from its
+                            launch                                                   */
+    uint64_t count;      /* number of embeddings (status CSTM_OK)                    */
+    double submit_s;     /* server clock, seconds since creation, at submission     */
+    double done_s;       /* ... when the result became available                    */
+    int32_t batch_size;  /* requests that shared its enumeration launch             */
+    int32_t lane;        /* the lane that ran it                                    */
+} cstm_request_result;
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t launches;   /* enumeration launches                                    */
+    uint64_t batched;    /* requests over all launches                              */
+    uint64_t peak_bytes; /* largest total charge of admitted requests               */
+    uint64_t in_use_bytes;
+    int32_t max_overlap; /* most lanes running launches at one time                 */
+    int32_t reserved;
+} cstm_server_stats;
+
+cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, uint64_t mem_budget, int32_t lanes,
+                               int32_t builders, int32_t max_batch, cstm_server** out);
+/* Queue a query (copied; same arguments as cstm_cst_build); *ticket names it.
+ * Only the sizes are checked here: a malformed query finishes with status
+ * CSTM_EINVAL. */
+cstm_status cstm_server_submit(cstm_server* srv, int32_t k, const int32_t* qlabel, int32_t m_q,
+                               const int32_t* qedges, uint64_t* ticket);
+/* Non-blocking: out->done = 0 while the request runs.  A finished result is
+ * handed out once; the ticket is unknown (CSTM_EINVAL) afterwards. */
+cstm_status cstm_server_poll(cstm_server* srv, uint64_t ticket, cstm_request_result* out);
+/* As poll, but waits up to timeout_s seconds (<= 0: until done). */
+cstm_status cstm_server_wait(cstm_server* srv, uint64_t ticket, double timeout_s, cstm_request_result* out);
+cstm_status cstm_server_get_stats(cstm_server* srv, cstm_server_stats* out);
+/* Finishes every submitted request, then stops the threads and frees the server. */
+void cstm_server_destroy(cstm_server* srv);
 
 /* Statistics of the last enumeration launch (cstm_enumerate or
  * cstm_batch_enumerate) made with this context. */

@@ -324,7 +324,7 @@ __global__ void k_enumerate(EnumArgs A) {
 // One launch over the partition images of nq partitioned CSTs; counts go to counts_dev[slot[q]].
 void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                             uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
-                            cstm_enum_stats* st, hipStream_t s) {
+                            const EnumOpts& opt, cstm_enum_stats* st, hipStream_t s) {
     int64_t total = 0;
     uint64_t max_blob = 0;
     for (int q = 0; q < nq; ++q) {
@@ -361,7 +361,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     A.row_cursor = row_cursor;
     A.stats = ctx->tune.collect_stats ? work + 1 : nullptr;
     A.stop = work + 6;
-    A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
+    A.deadline = opt.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)opt.deadline_ms : 0;
     const int waves = ctx->tune.waves_per_wg;
     const size_t lds = (size_t)cstm_align16(max_blob);
     static std::once_flag attr_once;
@@ -405,7 +405,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
 // Enumerate nq CSTs: pick LDS images or the HBM-resident CST per the tuning,
 // run at most one launch of each kind, and return per-CST counts.
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
-                        uint64_t* counts_host, uint64_t* rows_written, hipStream_t s) {
+                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s) {
     const cstm_tune T = ctx->tune;
     std::vector<cstm_cst*> lds_q, hbm_q;
     std::vector<int> lds_slot, hbm_slot;
@@ -440,10 +440,10 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
     cstm_enum_stats st{};
     if (!lds_q.empty())
         cstm_enumerate_lds_run(ctx, (int)lds_q.size(), lds_q.data(), lds_slot.data(), list, rows, cap, counts,
-                               row_cursor, &st, s);
+                               row_cursor, o, &st, s);
     if (!hbm_q.empty())
         cstm_enumerate_global_run(ctx, (int)hbm_q.size(), hbm_q.data(), hbm_slot.data(), list, rows, cap, counts,
-                                  row_cursor, &st, s);
+                                  row_cursor, o, &st, s);
     std::vector<unsigned long long> h(nq + 1);
     HIP_TRY(hipMemcpyAsync(h.data(), counts, (nq + 1) * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -455,12 +455,16 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
     if (rows_written) *rows_written = std::min<uint64_t>(h[nq], cap);
 }
 
-extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, uint64_t cap, uint64_t* count_out,
-                                      uint64_t* rows_written, void* stream) {
+extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* rows, uint64_t cap,
+                                      uint64_t* count_out, uint64_t* rows_written, double deadline_s, void* stream) {
     uint64_t count = 0;
     uint64_t written = 0;
     cstm_status st = cstm_guard([&] {
         CSTM_REQUIRE(cst, CSTM_EINVAL, "NULL cst");
+        CSTM_REQUIRE(deadline_s == deadline_s, CSTM_EINVAL, "deadline is NaN");
+        EnumOpts o;
+        o.limit = limit;
+        o.deadline_ms = deadline_s > 0 ? (int64_t)(deadline_s * 1e3) + 1 : cst->ctx->tune.deadline_ms;
         CSTM_REQUIRE(!list || rows || cap == 0, CSTM_EINVAL, "listing needs a row buffer");
         HIP_TRY(hipSetDevice(cst->ctx->device));
         hipStream_t s = stream ? (hipStream_t)stream : cst->stream;
@@ -469,7 +473,9 @@ extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, int32_t* rows, ui
         HIP_TRY(hipEventCreate(&b));
         HIP_TRY(hipEventRecord(a, s));
         cstm_cst* one[1] = {cst};
-        cstm_enumerate_run(cst->ctx, 1, one, list, rows, cap, &count, &written, s);
+        cstm_enumerate_run(cst->ctx, 1, one, list, rows, cap, &count, &written, o, s);
+        if (limit && count > limit) count = limit;  // a launch may pass the limit before it stops
+        if (limit && written > limit) written = limit;
         HIP_TRY(hipEventRecord(b, s));
         HIP_TRY(hipEventSynchronize(b));
         float ms = 0;
@@ -495,6 +501,8 @@ extern "C" cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst*
         for (int q = 0; q < nq; ++q) CSTM_REQUIRE(csts[q] && csts[q]->ctx == ctx, CSTM_EINVAL, "bad CST handle");
         if (nq == 0) return;
         HIP_TRY(hipSetDevice(ctx->device));
-        cstm_enumerate_run(ctx, nq, csts, 0, nullptr, 0, counts_out, nullptr, (hipStream_t)stream);
+        EnumOpts o;
+        o.deadline_ms = ctx->tune.deadline_ms;
+        cstm_enumerate_run(ctx, nq, csts, 0, nullptr, 0, counts_out, nullptr, o, (hipStream_t)stream);
     });
 }

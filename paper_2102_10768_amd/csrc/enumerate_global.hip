@@ -42,7 +42,7 @@ struct GQueue {
     GLine head;         // next ticket a consumer takes (may run ahead of tail: waiting consumers)
     GLine tail;         // next ticket a producer fills
     GLine outstanding;  // tasks pushed and not finished
-    GLine abort;        // 1: give up (idle limit), 2: deadline passed
+    GLine abort;        // 1: give up (idle limit), 2: deadline passed, 3: count limit reached
 };
 
 struct GArgs {
@@ -68,6 +68,7 @@ struct GArgs {
     int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
     int64_t donate_last_min;    // smallest last-level remainder worth donating
     int last_sum;               // > 0: count an unconstrained last level by list lengths
+    uint64_t limit;             // one query: stop once the count reaches this (0: none)
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -496,17 +497,27 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 // spreads fast), doubling up to donate_period while none do.
                 if (++since_check >= period) {
                     since_check = 0;
-                    int want = 0;
+                    int want = 0, added = 0;
+                    // with a count limit, publish the count found so far and stop once it is reached
+                    const bool publish = A.limit && cnt;
                     if (lane == 0) {
                         if (ld_rlx(&A.qu->abort.v)) want = -1;
                         else if (A.deadline && now_ticks() > A.deadline) {
                             atomicExch(&A.qu->abort.v, 2ull);
                             want = -1;
-                        } else if (A.donate_period > 0) {
+                        } else if (publish) {
+                            added = 1;
+                            if (atomicAdd(&A.counts[A.slot[cur_q]], (unsigned long long)cnt) + cnt >= A.limit) {
+                                atomicExch(&A.qu->abort.v, 3ull);
+                                want = -1;
+                            }
+                        }
+                        if (want == 0 && A.donate_period > 0) {
                             const unsigned long long t2 = ld_rlx(&A.qu->tail.v), h2 = ld_rlx(&A.qu->head.v);
                             want = (long long)(h2 - t2) > 0 ? 1 : 0;
                         }
                     }
+                    if (__shfl(added, 0)) cnt = 0;  // lane 0 added it to the query's count
                     want = __shfl(want, 0);
                     if (want < 0) break;
                     if (!want) period = period * 2 < max_period ? period * 2 : max_period;
@@ -602,7 +613,7 @@ __global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t
 // HBM; counts go to counts_dev[slot[q]].
 void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                                uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
-                               cstm_enum_stats* st, hipStream_t s) {
+                               const EnumOpts& o, cstm_enum_stats* st, hipStream_t s) {
     const int qlog = 20;
     const unsigned long long qcap = 1ull << qlog;
     std::vector<int64_t> first(nq + 1, 0), nroot(nq, 0), chunk(nq, 1);
@@ -671,7 +682,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.row_cursor = row_cursor;
     A.stats = ctx->tune.collect_stats ? work : nullptr;
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
-    A.deadline = ctx->tune.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)ctx->tune.deadline_ms : 0;
+    A.deadline = o.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)o.deadline_ms : 0;
+    A.limit = nq == 1 ? o.limit : 0;
     A.donate_period = ctx->tune.hbm_donate_period;
     A.donate_min = ctx->tune.hbm_donate_min > 0 ? ctx->tune.hbm_donate_min : 1;
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
@@ -713,5 +725,6 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         ctx->last_enum = *st;  // kept even when the launch is reported as failed below
     }
     CSTM_REQUIRE(fin.abort.v != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
+    if (fin.abort.v == 3) return;  // the limit was reached: the count is at least the limit
     CSTM_REQUIRE(!fin.abort.v && fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
 }

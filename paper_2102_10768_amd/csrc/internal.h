@@ -287,11 +287,16 @@ inline unsigned cstm_blocks(int64_t items, int per_block, unsigned cap = 1u << 2
 
 // Returns false (and leaves the CST unpartitioned) if the images would exceed max_total_bytes (0 = no limit).
 bool cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list, uint64_t max_total_bytes = 0);
+// Per-call options of an enumeration launch.
+struct EnumOpts {
+    uint64_t limit = 0;       // one query: stop once this many embeddings are found (0: find all)
+    int64_t deadline_ms = 0;  // stop the launch after this long (0: no limit)
+};
 void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                             uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
-                            cstm_enum_stats* st, hipStream_t s);
+                            const EnumOpts& o, cstm_enum_stats* st, hipStream_t s);
 void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                                uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
-                               cstm_enum_stats* st, hipStream_t s);
+                               const EnumOpts& o, cstm_enum_stats* st, hipStream_t s);
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
-                        uint64_t* counts_host, uint64_t* rows_written, hipStream_t s);
+                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s);

@@ -65,6 +65,32 @@ class cstm_enum_stats(ctypes.Structure):
     ]
 
 
+class cstm_request_result(ctypes.Structure):
+    _fields_ = [
+        ("done", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("submit_s", ctypes.c_double),
+        ("done_s", ctypes.c_double),
+        ("batch_size", ctypes.c_int32),
+        ("lane", ctypes.c_int32),
+    ]
+
+
+class cstm_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
+        ("batched", ctypes.c_uint64),
+        ("peak_bytes", ctypes.c_uint64),
+        ("in_use_bytes", ctypes.c_uint64),
+        ("max_overlap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class cstm_cst_info(ctypes.Structure):
     _fields_ = [
         ("k", ctypes.c_int32),
@@ -92,6 +118,8 @@ EXPORTS = [
     "cstm_cst_build", "cstm_cst_partition", "cstm_cst_info_get", "cstm_cst_candidates",
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
     "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
+    "cstm_server_create", "cstm_server_submit", "cstm_server_poll", "cstm_server_wait", "cstm_server_get_stats",
+    "cstm_server_destroy",
 ]
 
 _lib = None
@@ -126,13 +154,20 @@ def load_library():
         "cstm_cst_partition": (st, [P, U64, I32, ctypes.POINTER(I64)]),
         "cstm_cst_info_get": (st, [P, ctypes.POINTER(cstm_cst_info)]),
         "cstm_cst_candidates": (st, [P, I32, P, I64, ctypes.POINTER(I64)]),
-        "cstm_enumerate": (st, [P, ctypes.c_int, P, U64, ctypes.POINTER(U64), ctypes.POINTER(U64), P]),
+        "cstm_enumerate": (st, [P, ctypes.c_int, U64, P, U64, ctypes.POINTER(U64), ctypes.POINTER(U64),
+                                ctypes.c_double, P]),
         "cstm_batch_enumerate": (st, [P, I32, P, P, P]),
         "cstm_cst_times": (st, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
         "cstm_cst_free": (None, [P]),
         "cstm_ctx_last_enum_stats": (st, [P, ctypes.POINTER(cstm_enum_stats)]),
         "cstm_cst_estimate": (st, [P, I32, P, I32, P, ctypes.POINTER(U64)]),
+        "cstm_server_create": (st, [P, P, U64, I32, I32, I32, ctypes.POINTER(P)]),
+        "cstm_server_submit": (st, [P, I32, P, I32, P, ctypes.POINTER(U64)]),
+        "cstm_server_poll": (st, [P, U64, ctypes.POINTER(cstm_request_result)]),
+        "cstm_server_wait": (st, [P, U64, ctypes.c_double, ctypes.POINTER(cstm_request_result)]),
+        "cstm_server_get_stats": (st, [P, ctypes.POINTER(cstm_server_stats)]),
+        "cstm_server_destroy": (None, [P]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -332,23 +367,25 @@ class CST:
         _check(lib.cstm_cst_candidates(self.handle, u, out.ctypes.data, n.value, ctypes.byref(n)))
         return out
 
-    def count(self, stream=None) -> int:
+    def count(self, stream=None, limit: int = 0, deadline_s: float = 0.0) -> int:
+        """Number of embeddings; with ``limit`` > 0, exactly min(total, limit)."""
         c, w = ctypes.c_uint64(), ctypes.c_uint64()
-        _check(load_library().cstm_enumerate(self.handle, 0, None, 0, ctypes.byref(c), ctypes.byref(w),
-                                             _stream_ptr(stream)))
+        _check(load_library().cstm_enumerate(self.handle, 0, int(limit), None, 0, ctypes.byref(c), ctypes.byref(w),
+                                             float(deadline_s), _stream_ptr(stream)))
         return c.value
 
-    def list(self, cap: int, stream=None, allow_overflow: bool = False):
+    def list(self, cap: int, stream=None, allow_overflow: bool = False, limit: int = 0, deadline_s: float = 0.0):
         """Returns (count, rows): rows is a (min(count, cap), k) int32 CUDA tensor.
 
         Raises on overflow (count > cap) unless ``allow_overflow``; the count is exact either way.
+        With ``limit`` > 0 the count is min(total, limit) and at most that many rows are returned.
         """
         import torch
 
         rows = torch.empty((max(cap, 1), self.k), dtype=torch.int32, device=f"cuda:{self.ctx.device}")
         c, w = ctypes.c_uint64(), ctypes.c_uint64()
-        st = load_library().cstm_enumerate(self.handle, 1, rows.data_ptr(), int(cap), ctypes.byref(c),
-                                           ctypes.byref(w), _stream_ptr(stream))
+        st = load_library().cstm_enumerate(self.handle, 1, int(limit), rows.data_ptr(), int(cap), ctypes.byref(c),
+                                           ctypes.byref(w), float(deadline_s), _stream_ptr(stream))
         if not (allow_overflow and st == EOVERFLOW):
             _check(st)
         return c.value, rows[: w.value]
@@ -362,6 +399,70 @@ class CST:
         if getattr(self, "handle", None):
             load_library().cstm_cst_free(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """``cstm_server_*``: the library's request loop over a resident graph.
+
+    ``submit`` queues a query and returns a ticket; ``wait``/``poll`` return a
+    dict (``done``, ``status``, ``count``, ``submit_s``, ``done_s`` on the
+    server's clock, ``batch_size``, ``lane``) once, when the request is done.
+    """
+
+    def __init__(self, ctx: Context, graph: "Graph", mem_budget: int = 64 << 30, lanes: int = 2,
+                 builders: int = 4, max_batch: int = 256):
+        self.ctx = ctx
+        self.graph = graph
+        h = ctypes.c_void_p()
+        _check(load_library().cstm_server_create(ctx.handle, graph.handle, int(mem_budget), int(lanes),
+                                                 int(builders), int(max_batch), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+
+    def submit(self, qlabel, qedges) -> int:
+        ql = np.ascontiguousarray(qlabel, dtype=np.int32)
+        qe = np.ascontiguousarray(np.asarray(qedges, dtype=np.int32).reshape(-1, 2))
+        t = ctypes.c_uint64()
+        _check(load_library().cstm_server_submit(self.handle, int(ql.shape[0]), ql.ctypes.data, int(qe.shape[0]),
+                                                 qe.ctypes.data if qe.size else None, ctypes.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _result(r: cstm_request_result) -> dict:
+        return {f: getattr(r, f) for f, _ in cstm_request_result._fields_}
+
+    def poll(self, ticket: int) -> dict:
+        r = cstm_request_result()
+        _check(load_library().cstm_server_poll(self.handle, int(ticket), ctypes.byref(r)))
+        return self._result(r)
+
+    def wait(self, ticket: int, timeout_s: float = 0.0) -> dict:
+        r = cstm_request_result()
+        _check(load_library().cstm_server_wait(self.handle, int(ticket), float(timeout_s), ctypes.byref(r)))
+        return self._result(r)
+
+    def stats(self) -> dict:
+        v = cstm_server_stats()
+        _check(load_library().cstm_server_get_stats(self.handle, ctypes.byref(v)))
+        return {f: getattr(v, f) for f, _ in cstm_server_stats._fields_}
+
+    def close(self):
+        """Finish every submitted request, then free the server."""
+        if getattr(self, "handle", None):
+            load_library().cstm_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -1,5 +1,10 @@
 """Request loop for matching queries against one resident data graph.
 
+The library implements this loop natively (``cstm_server_*``, bound as
+``cstm.Server``); ``replay_native`` drives it with a request stream.  The
+``Server`` class below is the same policy over a pluggable backend, used to
+test the policy on the host and to run it over custom backends.
+
 Requests (query graphs) arrive one at a time.  The loop
 
 * admits them in arrival order while their CSTs fit a device-memory budget
@@ -298,6 +303,33 @@ def replay(server: Server, arrivals, queries, *, clock=time.perf_counter):
     for r in reqs:
         r.wait()
     return reqs
+
+
+def replay_native(server, arrivals, queries, *, clock=time.perf_counter):
+    """Submit ``queries[i]`` to a ``cstm.Server`` at ``arrivals[i]`` seconds after
+    the start, wait for every result, and return them as ``Request`` records
+    timed on the server's own clock (submission to result)."""
+    start = clock()
+    tickets = []
+    for t, q in zip(arrivals, queries):
+        now = clock() - start
+        if now < t:
+            time.sleep(t - now)
+        tickets.append((server.submit(q.qlabel, q.qedges), q))
+    out = []
+    for rid, (tk, q) in enumerate(tickets):
+        res = server.wait(tk)
+        r = Request(rid, q, res["submit_s"])
+        r.t_done = res["done_s"]
+        r.batch_size = res["batch_size"]
+        r.lane = res["lane"]
+        if res["status"] == 0:
+            r.count = int(res["count"])
+        else:
+            r.error = f"status {res['status']}"
+        r._event.set()
+        out.append(r)
+    return out
 
 
 def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:

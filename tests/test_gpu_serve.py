@@ -61,3 +61,50 @@ def test_served_results_equal_results_alone(name, n_req, qps):
         assert r.error is None, r.error
         assert r.count == alone[int(p)]
     assert srv.peak_bytes <= 8 << 30
+
+
+@pytest.mark.parametrize("name,n_req,qps", [("c1", 200, 4000.0), ("c2", 24, 40.0)])
+def test_native_server_results_equal_results_alone(name, n_req, qps):
+    """cstm_server_*: every served count equals the stored count of the query alone."""
+    from paper_2102_10768_amd import cstm, serve
+
+    W = _load(name)
+    g = make_graph(W["workload"]["graph"])
+    G = gpu_graph(g, "hbm")
+    c = ctx("hbm")
+    pool = [Query.from_dict(d) for d in W["queries"]]
+    expected = [int(d["count"]) for d in W["queries"]]
+    rng = np.random.Generator(np.random.PCG64(205))
+    if name == "c2":
+        picks = rng.choice(np.argsort(expected)[: len(pool) // 2], size=n_req)
+    else:
+        picks = rng.integers(0, len(pool), size=n_req)
+    arr = serve.poisson_arrivals(n_req, qps, 206)
+    with cstm.Server(c, G, mem_budget=8 << 30, lanes=2, builders=4) as srv:
+        reqs = serve.replay_native(srv, arr, [pool[int(p)] for p in picks])
+        st = srv.stats()
+        # a malformed query finishes with its own error status, others are unaffected
+        bad = srv.submit([0, 1, 2], [(0, 1)])  # disconnected
+        res = srv.wait(bad)
+        assert res["done"] == 1 and res["status"] == cstm.EINVAL
+        with pytest.raises(cstm.CstmError):
+            srv.poll(bad)  # a result is handed out once
+    say(f"{name}: {serve.summarize(reqs)} stats {st}")
+    for r, p in zip(reqs, picks):
+        assert r.error is None, r.error
+        assert r.count == expected[int(p)]
+    assert st["completed"] == n_req and st["peak_bytes"] <= 8 << 30
+
+
+def test_native_server_refuses_a_request_larger_than_the_budget():
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c1")
+    g = make_graph(W["workload"]["graph"])
+    G = gpu_graph(g, "hbm")
+    q = Query.from_dict(W["queries"][0])
+    est = G.estimate_bytes(q.qlabel, q.qedges)
+    with cstm.Server(ctx("hbm"), G, mem_budget=est, lanes=1, builders=1) as srv:
+        t = srv.submit(q.qlabel, q.qedges)
+        res = srv.wait(t)
+    assert res["status"] == cstm.ENOMEM and res["count"] == 0

@@ -225,3 +225,56 @@ def test_deadline_stops_an_on_chip_launch():
     assert c3.count() == cf.clique_host_count(120, 3)
     cs.close()
     c3.close()
+
+
+def test_count_limit_returns_min_of_total_and_limit():
+    """A count limit stops the search early; the result is exactly min(total, limit)."""
+    import time
+
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c2")
+    g, G = _graph("c2", W, "hbm")
+    heavy = max(W["queries"], key=lambda d: d["count"])
+    q = Query.from_dict(heavy)
+    c = cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges)
+    total = heavy["count"]
+    t = time.perf_counter()
+    assert c.count(limit=1_000_000) == 1_000_000
+    early = time.perf_counter() - t
+    t = time.perf_counter()
+    assert c.count() == total
+    full = time.perf_counter() - t
+    say(f"limit 1e6: {early * 1e3:.1f} ms, full count: {full * 1e3:.1f} ms")
+    assert early < full
+    for lim in (1, total - 1, total, total + 7):
+        assert c.count(limit=lim) == min(total, lim)
+    n, rows = c.list(4096, allow_overflow=True, limit=100)
+    assert n == 100 and rows.shape[0] == 100
+    _check_rows(g, q, rows.cpu().numpy())
+    c.close()
+
+    Ws = _load("c1")
+    gs, Gs = _graph("c1", Ws, "lds")
+    for d in Ws["queries"][:4]:
+        qs = Query.from_dict(d)
+        cl = cstm.CST(ctx("lds"), Gs, qs.qlabel, qs.qedges)
+        cl.partition(4096)
+        for lim in (1, max(1, d["count"] // 2), d["count"] + 1):
+            assert cl.count(limit=lim) == min(d["count"], lim)
+        cl.close()
+
+
+def test_per_call_deadline():
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c2")
+    g, G = _graph("c2", W, "hbm")
+    heavy = max(W["queries"], key=lambda d: d["count"])
+    q = Query.from_dict(heavy)
+    c = cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges)
+    with pytest.raises(cstm.CstmError) as ei:
+        c.count(deadline_s=0.001)
+    assert ei.value.status == cstm.ETIMEOUT
+    assert c.count(deadline_s=30.0) == heavy["count"]
+    c.close()
