@@ -28,14 +28,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per launch of the enumeration kernel from the committed counter
-    summary, or None when the kernel source has changed since it was taken."""
+    summary of the power-law workload, or None for another workload or when the
+    kernel source has changed since the counters were taken."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_2102_10768_amd", "csrc", "enumerate_global.hip")
     prof = os.path.join(ROOT, "profiles", "c2_power_law_hbm_counters.md")
-    if not os.path.exists(prof):
+    if workload != "c2" or not os.path.exists(prof):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     vals = {}
@@ -70,6 +71,7 @@ def main():
     ap.add_argument("--rates", default="", help="arrival rates (queries/s) for --serve (default: the workload's)")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests per rate for --serve (default: the workload's)")
     ap.add_argument("--mem-budget-gb", type=float, default=0.0, help="admission budget for --serve (default: the workload's)")
+    ap.add_argument("--batch-wait-us", type=int, default=2000, help="--serve: lanes under load wait this long for more CSTs")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
@@ -245,7 +247,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(a.workload),
             "algorithmic_bytes_per_step": alg_bytes,
             "launches_per_step": launches,
             "avg_launch_ms": kern_ms / max(1, launches),
@@ -307,7 +309,7 @@ def serve_main(a, W, g, queries, expected):
         picks = np.random.Generator(np.random.PCG64(301 + i)).integers(0, len(queries), size=n)
         qs = [queries[int(p)] for p in picks]
         want = [expected[int(p)] for p in picks]
-        with cstm.Server(ctx, G, mem_budget=budget, lanes=2, builders=4) as srv:
+        with cstm.Server(ctx, G, mem_budget=budget, lanes=2, builders=4, batch_wait_us=a.batch_wait_us) as srv:
             served = serve.replay_native(srv, arr, qs)
             sst = srv.stats()
         s_srv = serve.summarize(served)
@@ -341,7 +343,9 @@ def serve_main(a, W, g, queries, expected):
             "workload": W["workload"]["title"],
             "name": a.workload,
             "form": "served (cstm_server): Poisson arrivals, admission by CST footprint bound, 4 CST builder "
-                    "threads, 2 enumeration lanes with batched persistent launches; value is at the highest rate",
+                    "threads, 2 enumeration lanes with batched persistent launches (batching window under load); "
+                    "value is at the highest rate",
+            "batch_wait_us": a.batch_wait_us,
             "query_pool": len(queries),
             "mem_budget_bytes": budget,
         },

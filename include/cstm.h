@@ -247,10 +247,13 @@ cstm_status cstm_cst_candidates(const cstm_cst* cst, int32_t u, int32_t* out, in
 cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* rows, uint64_t cap,
                            uint64_t* count_out, uint64_t* rows_written, double deadline_s, void* stream);
 
-/* Enumerate (count) many partitioned CSTs in one persistent launch that draws
- * partitions from a device work queue.  counts_out[nq] is a host array. */
-cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
-                                 void* stream);
+/* Count the embeddings of many CSTs in one persistent launch that draws work
+ * from a device queue (the batched form).  limits (host, may be NULL): per
+ * CST, 0 = count all, > 0 = stop that CST's search once it has that many
+ * (counts_out[i] is then exactly min(total_i, limits[i])).  counts_out[nq] is
+ * a host array. */
+cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, const uint64_t* limits,
+                                 uint64_t* counts_out, void* stream);
 
 /* ---------------------------------------------------------------- serving
  *
@@ -265,6 +268,10 @@ cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* cst
  * count does not depend on which requests share its launch.  The server is
  * thread-safe; it uses the context's tuning (deadline_ms applies per launch).
  * Zero or negative lanes / builders / max_batch take the defaults 2 / 4 / 256.
+ * batch_wait_us: when a lane finds built CSTs while another lane is already
+ * running a launch (the server is under load) and more requests are on their
+ * way, it waits up to this long for more to join its launch; an idle server
+ * launches at once (0: never wait).
  * Errors: CSTM_EINVAL for NULL arguments or a graph of another context. */
 typedef struct cstm_server cstm_server;
 typedef struct {
@@ -290,12 +297,13 @@ typedef struct {
 } cstm_server_stats;
 
 cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, uint64_t mem_budget, int32_t lanes,
-                               int32_t builders, int32_t max_batch, cstm_server** out);
+                               int32_t builders, int32_t max_batch, int32_t batch_wait_us, cstm_server** out);
 /* Queue a query (copied; same arguments as cstm_cst_build); *ticket names it.
- * Only the sizes are checked here: a malformed query finishes with status
- * CSTM_EINVAL. */
+ * limit: 0 = count every embedding, > 0 = the result is min(total, limit)
+ * and the search stops once it is reached.  Only the sizes are checked here:
+ * a malformed query finishes with status CSTM_EINVAL. */
 cstm_status cstm_server_submit(cstm_server* srv, int32_t k, const int32_t* qlabel, int32_t m_q,
-                               const int32_t* qedges, uint64_t* ticket);
+                               const int32_t* qedges, uint64_t limit, uint64_t* ticket);
 /* Non-blocking: out->done = 0 while the request runs.  A finished result is
  * handed out once; the ticket is unknown (CSTM_EINVAL) afterwards. */
 cstm_status cstm_server_poll(cstm_server* srv, uint64_t ticket, cstm_request_result* out);

@@ -51,6 +51,7 @@ def _load():
             ctypes.c_int64, p, p, p, p,  # n, row_ptr, col, label, label-grouped col
             ctypes.c_int32, p, ctypes.c_int32, p,  # k, qlabel, m_q, qedges
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,  # degfilter, threads, deadline, budget
+            ctypes.c_uint64,  # limit
             ctypes.c_int, p, ctypes.c_uint64, ctypes.c_int,  # list, rows, cap, mutate
             p, p, p, p,  # count, nodes, rows_written, threads_used
         ]
@@ -101,11 +102,13 @@ def _c(a, dtype):
 
 def match(g, q, *, list_rows: bool = False, cap: int | None = None, degree_filter: bool = True,
           threads: int = 0, deadline_s: float = 0.0, node_budget: int = 0, mutate: int = 0,
-          lcol: np.ndarray | None = None) -> MatchResult:
+          lcol: np.ndarray | None = None, limit: int = 0) -> MatchResult:
     """Count (and with ``list_rows`` list, sorted) all embeddings of ``q`` in ``g``.
 
     ``g`` has ``n``, ``row_ptr``, ``col``, ``label``; ``q`` has ``qlabel``, ``qedges``.
     ``lcol`` (optional) is :func:`label_grouped_col` of ``g``: same result, less scanning.
+    ``limit`` > 0 (counting only) stops once that many embeddings were found;
+    the count is then exactly min(total, limit).
     Raises ``ValueError`` on an invalid query.  A ``TIMEOUT`` status means the
     count is only a lower bound.
     """
@@ -130,7 +133,7 @@ def match(g, q, *, list_rows: bool = False, cap: int | None = None, degree_filte
     st = lib.oracle_match(
         int(g.n), row_ptr.ctypes.data, col.ctypes.data, label.ctypes.data,
         lcol.ctypes.data if lcol is not None else None, k, qlabel.ctypes.data, int(qedges.shape[0]), qedges.ctypes.data,
-        int(bool(degree_filter)), int(threads), float(deadline_s), int(node_budget),
+        int(bool(degree_filter)), int(threads), float(deadline_s), int(node_budget), int(limit),
         int(bool(list_rows)), rows.ctypes.data if rows is not None else None, cap, int(mutate),
         ctypes.byref(cnt), ctypes.byref(nodes), ctypes.byref(written), ctypes.byref(used),
     )

@@ -70,7 +70,9 @@ typedef struct {
     int32_t* roots;
     _Atomic int64_t next_root;
     _Atomic uint64_t nodes_total;
-    _Atomic int stop;
+    _Atomic int stop;         /* 1 budget, 2 deadline, 3 out of memory, 4 limit */
+    uint64_t limit;           /* > 0: stop once this many embeddings are found  */
+    _Atomic uint64_t found;   /* embeddings published by the workers            */
     uint64_t node_budget;
     double deadline; /* absolute CLOCK_MONOTONIC seconds; 0 = none */
 } ctx_t;
@@ -79,6 +81,7 @@ typedef struct {
     ctx_t* c;
     int32_t map[OR_MAXK];
     uint64_t count;
+    uint64_t published;       /* part of count already added to c->found        */
     uint64_t nodes;
     uint64_t unflushed;
     int32_t* rows;
@@ -107,6 +110,11 @@ static void flush_nodes(worker_t* w) {
     ctx_t* c = w->c;
     uint64_t tot = atomic_fetch_add(&c->nodes_total, w->unflushed) + w->unflushed;
     w->unflushed = 0;
+    if (c->limit) {
+        uint64_t f = atomic_fetch_add(&c->found, w->count - w->published) + (w->count - w->published);
+        w->published = w->count;
+        if (f >= c->limit) atomic_store(&c->stop, 4);
+    }
     if (c->node_budget && tot > c->node_budget) atomic_store(&c->stop, 1);
     if (c->deadline > 0 && now_s() > c->deadline) atomic_store(&c->stop, 2);
 }
@@ -137,6 +145,7 @@ static void visit(worker_t* w, int depth) {
     if (depth == c->k) {
         w->count++;
         if (c->list) emit(w);
+        if (c->limit && w->count - w->published >= c->limit) flush_nodes(w);
         return;
     }
     const int u = c->order[depth];
@@ -224,6 +233,9 @@ int oracle_num_cores(void) {
  *   degree_filter: 1 prunes candidates with d_G(v) < d_q(u).
  *   nthreads: worker threads, 0 = all online cores; the number used is written
  *       to *threads_used.
+ *   limit (0: none): stop once at least limit embeddings were found; the call
+ *       then returns OR_OK with *count_out = limit, which is min(total, limit)
+ *       exactly (listing is not combined with a limit).
  *   deadline_s (<= 0: none) and node_budget (0: none): on expiry the call
  *       returns OR_ETIMEOUT and *count_out is a lower bound.  The budget caps
  *       the work done: partial embeddings visited (root level included) plus
@@ -237,18 +249,19 @@ int oracle_num_cores(void) {
  */
 int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const int32_t* label,
                  const int32_t* lcol, int32_t k, const int32_t* qlabel, int32_t m_q, const int32_t* qedges,
-                 int degree_filter, int nthreads, double deadline_s, uint64_t node_budget,
+                 int degree_filter, int nthreads, double deadline_s, uint64_t node_budget, uint64_t limit,
                  int list, int32_t* rows, uint64_t cap, int mutate,
                  uint64_t* count_out, uint64_t* nodes_out, uint64_t* rows_written, int* threads_used) {
     if (count_out) *count_out = 0;
     if (nodes_out) *nodes_out = 0;
     if (rows_written) *rows_written = 0;
-    if (k < 1 || k > OR_MAXK || n < 0 || m_q < 0) return OR_EINVAL;
+    if (k < 1 || k > OR_MAXK || n < 0 || m_q < 0 || (limit && list)) return OR_EINVAL;
     ctx_t* c = (ctx_t*)calloc(1, sizeof(ctx_t));
     if (!c) return OR_ENOMEM;
     c->n = n; c->rp = row_ptr; c->col = col; c->lab = label; c->lcol = lcol; c->k = k;
     c->degfilter = degree_filter; c->mutate = mutate; c->list = list;
     c->node_budget = node_budget;
+    c->limit = limit;
     c->deadline = deadline_s > 0 ? now_s() + deadline_s : 0;
     unsigned char adj[OR_MAXK][OR_MAXK];
     memset(adj, 0, sizeof(adj));
@@ -334,6 +347,7 @@ int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const in
     uint64_t nodes = atomic_load(&c->nodes_total);
     int status = OR_OK;
     if (oom) status = OR_ENOMEM;
+    else if (limit && count >= limit) count = limit;  /* reached: min(total, limit) = limit */
     else if (atomic_load(&c->stop) || (node_budget && nodes > node_budget)) status = OR_ETIMEOUT;
 
     if (list && status == OR_OK && total_rows) {

@@ -451,7 +451,11 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
         std::lock_guard<std::mutex> lk(ctx->ws_mu);
         ctx->last_enum = st;
     }
-    for (int q = 0; q < nq; ++q) counts_host[q] = h[q];
+    for (int q = 0; q < nq; ++q) {
+        counts_host[q] = h[q];
+        // a launch passes a limit before it stops, and LDS mode counts everything
+        if (o.limits && o.limits[q] && counts_host[q] > o.limits[q]) counts_host[q] = o.limits[q];
+    }
     if (rows_written) *rows_written = std::min<uint64_t>(h[nq], cap);
 }
 
@@ -463,7 +467,7 @@ extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, i
         CSTM_REQUIRE(cst, CSTM_EINVAL, "NULL cst");
         CSTM_REQUIRE(deadline_s == deadline_s, CSTM_EINVAL, "deadline is NaN");
         EnumOpts o;
-        o.limit = limit;
+        o.limits = limit ? &limit : nullptr;
         o.deadline_ms = deadline_s > 0 ? (int64_t)(deadline_s * 1e3) + 1 : cst->ctx->tune.deadline_ms;
         CSTM_REQUIRE(!list || rows || cap == 0, CSTM_EINVAL, "listing needs a row buffer");
         HIP_TRY(hipSetDevice(cst->ctx->device));
@@ -474,7 +478,6 @@ extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, i
         HIP_TRY(hipEventRecord(a, s));
         cstm_cst* one[1] = {cst};
         cstm_enumerate_run(cst->ctx, 1, one, list, rows, cap, &count, &written, o, s);
-        if (limit && count > limit) count = limit;  // a launch may pass the limit before it stops
         if (limit && written > limit) written = limit;
         HIP_TRY(hipEventRecord(b, s));
         HIP_TRY(hipEventSynchronize(b));
@@ -493,8 +496,8 @@ extern "C" cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, i
     return st;
 }
 
-extern "C" cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, uint64_t* counts_out,
-                                            void* stream) {
+extern "C" cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, const uint64_t* limits,
+                                            uint64_t* counts_out, void* stream) {
     return cstm_guard([&] {
         CSTM_REQUIRE(ctx && (nq == 0 || (csts && counts_out)), CSTM_EINVAL, "NULL argument");
         CSTM_REQUIRE(nq >= 0, CSTM_EINVAL, "negative query count");
@@ -502,6 +505,7 @@ extern "C" cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst*
         if (nq == 0) return;
         HIP_TRY(hipSetDevice(ctx->device));
         EnumOpts o;
+        o.limits = limits;
         o.deadline_ms = ctx->tune.deadline_ms;
         cstm_enumerate_run(ctx, nq, csts, 0, nullptr, 0, counts_out, nullptr, o, (hipStream_t)stream);
     });

@@ -42,7 +42,7 @@ struct GQueue {
     GLine head;         // next ticket a consumer takes (may run ahead of tail: waiting consumers)
     GLine tail;         // next ticket a producer fills
     GLine outstanding;  // tasks pushed and not finished
-    GLine abort;        // 1: give up (idle limit), 2: deadline passed, 3: count limit reached
+    GLine abort;        // 1: give up (idle limit), 2: deadline passed
 };
 
 struct GArgs {
@@ -68,7 +68,8 @@ struct GArgs {
     int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
     int64_t donate_last_min;    // smallest last-level remainder worth donating
     int last_sum;               // > 0: count an unconstrained last level by list lengths
-    uint64_t limit;             // one query: stop once the count reaches this (0: none)
+    const unsigned long long* limits;  // per query: stop once its count reaches this (0: none); nullptr: none
+    unsigned int* qstop;               // per query: set once its limit was reached
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -369,6 +370,12 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
         const GTask* T = &A.tasks[slot];
         const int q = T->q;
         const int j = T->depth;
+        if (A.qstop && ld_rlx(&A.qstop[q])) {
+            // this query already found its limit: drop the task
+            if (lane == 0) atomicAdd(&A.qu->outstanding.v, ~0ull);
+            t_busy += now_ticks() - w1;
+            continue;
+        }
         int64_t lo = T->lo, hi = T->hi;
         int32_t pre = lane < CSTM_MAX_K ? T->prefix[lane] : 0;
         ++ntasks;
@@ -498,18 +505,22 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 if (++since_check >= period) {
                     since_check = 0;
                     int want = 0, added = 0;
-                    // with a count limit, publish the count found so far and stop once it is reached
-                    const bool publish = A.limit && cnt;
+                    // with a count limit, publish the count found so far; once the
+                    // query's count reaches its limit, every task of it stops
+                    const unsigned long long lim = A.limits ? A.limits[q] : 0ull;
+                    const bool publish = lim && cnt;
                     if (lane == 0) {
                         if (ld_rlx(&A.qu->abort.v)) want = -1;
                         else if (A.deadline && now_ticks() > A.deadline) {
                             atomicExch(&A.qu->abort.v, 2ull);
                             want = -1;
+                        } else if (lim && ld_rlx(&A.qstop[q])) {
+                            want = -2;
                         } else if (publish) {
                             added = 1;
-                            if (atomicAdd(&A.counts[A.slot[cur_q]], (unsigned long long)cnt) + cnt >= A.limit) {
-                                atomicExch(&A.qu->abort.v, 3ull);
-                                want = -1;
+                            if (atomicAdd(&A.counts[A.slot[q]], (unsigned long long)cnt) + cnt >= lim) {
+                                __hip_atomic_store(&A.qstop[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                want = -2;
                             }
                         }
                         if (want == 0 && A.donate_period > 0) {
@@ -637,7 +648,9 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const size_t off_desc = up(off_work + 8 * sizeof(unsigned long long));
     const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
     const size_t off_slot = up(off_meta + (3 * (size_t)nq + 1) * sizeof(int64_t));
-    const size_t need = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t off_lim = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t off_stop = up(off_lim + (size_t)nq * sizeof(unsigned long long));
+    const size_t need = up(off_stop + (size_t)nq * sizeof(unsigned int));
     const size_t ready_b = qcap * sizeof(unsigned int);
     struct WsHold {
         cstm_ctx* ctx;
@@ -652,6 +665,19 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     CstDev* descs = (CstDev*)(ws + off_desc);
     int64_t* meta = (int64_t*)(ws + off_meta);
     int32_t* dslot = (int32_t*)(ws + off_slot);
+    unsigned long long* dlim = (unsigned long long*)(ws + off_lim);
+    unsigned int* dstop = (unsigned int*)(ws + off_stop);
+    bool any_limit = false;
+    std::vector<unsigned long long> lim(nq, 0);
+    if (o.limits)
+        for (int q = 0; q < nq; ++q) {
+            lim[q] = o.limits[slot[q]];
+            any_limit |= lim[q] != 0;
+        }
+    if (any_limit) {
+        HIP_TRY(hipMemcpyAsync(dlim, lim.data(), (size_t)nq * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemsetAsync(dstop, 0, (size_t)nq * 4, s));
+    }
     for (int q = 0; q < nq; ++q)
         HIP_TRY(hipMemcpyAsync(descs + q, &csts[q]->host_desc, sizeof(CstDev), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(ready, 0, ready_b, s));
@@ -683,7 +709,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.stats = ctx->tune.collect_stats ? work : nullptr;
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
     A.deadline = o.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)o.deadline_ms : 0;
-    A.limit = nq == 1 ? o.limit : 0;
+    A.limits = any_limit ? dlim : nullptr;
+    A.qstop = any_limit ? dstop : nullptr;
     A.donate_period = ctx->tune.hbm_donate_period;
     A.donate_min = ctx->tune.hbm_donate_min > 0 ? ctx->tune.hbm_donate_min : 1;
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
@@ -725,6 +752,5 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         ctx->last_enum = *st;  // kept even when the launch is reported as failed below
     }
     CSTM_REQUIRE(fin.abort.v != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
-    if (fin.abort.v == 3) return;  // the limit was reached: the count is at least the limit
     CSTM_REQUIRE(!fin.abort.v && fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
 }

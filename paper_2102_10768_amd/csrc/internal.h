@@ -289,8 +289,8 @@ inline unsigned cstm_blocks(int64_t items, int per_block, unsigned cap = 1u << 2
 bool cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list, uint64_t max_total_bytes = 0);
 // Per-call options of an enumeration launch.
 struct EnumOpts {
-    uint64_t limit = 0;       // one query: stop once this many embeddings are found (0: find all)
-    int64_t deadline_ms = 0;  // stop the launch after this long (0: no limit)
+    const uint64_t* limits = nullptr;  // per CST of the call: stop once it has this many embeddings (0: all)
+    int64_t deadline_ms = 0;           // stop the launch after this long (0: no limit)
 };
 void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                             uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,

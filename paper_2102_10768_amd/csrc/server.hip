@@ -29,6 +29,7 @@ struct Request {
     int32_t k = 0;
     int32_t qlabel[CSTM_MAX_K] = {};
     std::vector<int32_t> qedges;
+    uint64_t limit = 0;
     uint64_t charge = 0;
     cstm_cst* cst = nullptr;
     bool built = false, done = false;
@@ -42,6 +43,7 @@ struct cstm_server {
     const cstm_graph* g = nullptr;
     uint64_t budget = 0;
     int max_batch = 256;
+    int64_t batch_wait_us = 0;
     Clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;
@@ -143,7 +145,7 @@ struct cstm_server {
         (void)hipSetDevice(ctx->device);
         std::vector<Request*> batch;
         std::vector<cstm_cst*> csts;
-        std::vector<uint64_t> counts;
+        std::vector<uint64_t> counts, limits;
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -151,6 +153,14 @@ struct cstm_server {
                 if (ready.empty()) {
                     cv.notify_all();
                     return;
+                }
+                // Under load (another lane already running) a short wait lets more
+                // built CSTs join this launch; an idle server launches at once.
+                if (batch_wait_us > 0 && busy_lanes > 0 && (int)ready.size() < max_batch &&
+                    (!pending.empty() || unbuilt > 0)) {
+                    const auto until = Clock::now() + std::chrono::microseconds(batch_wait_us);
+                    cv.wait_until(lk, until, [&] { return (int)ready.size() >= max_batch || busy_lanes == 0; });
+                    if (ready.empty()) continue;  // another lane took them meanwhile
                 }
                 batch.clear();
                 while (!ready.empty() && (int)batch.size() < max_batch) {
@@ -163,14 +173,19 @@ struct cstm_server {
                 st.batched += batch.size();
             }
             csts.clear();
+            limits.clear();
+            bool any_limit = false;
             for (Request* r : batch) {
                 csts.push_back(r->cst);
+                limits.push_back(r->limit);
+                any_limit |= r->limit != 0;
                 r->res.batch_size = (int32_t)batch.size();
                 r->res.lane = lane;
             }
             counts.assign(batch.size(), 0);
             cstm_status e = cstm_guard([&] {
                 EnumOpts o;
+                o.limits = any_limit ? limits.data() : nullptr;
                 o.deadline_ms = ctx->tune.deadline_ms;
                 cstm_enumerate_run(ctx, (int)csts.size(), csts.data(), 0, nullptr, 0, counts.data(), nullptr, o, s);
             });
@@ -184,7 +199,8 @@ struct cstm_server {
 };
 
 extern "C" cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, uint64_t mem_budget, int32_t lanes,
-                                          int32_t builders, int32_t max_batch, cstm_server** out) {
+                                          int32_t builders, int32_t max_batch, int32_t batch_wait_us,
+                                          cstm_server** out) {
     cstm_server* srv = nullptr;
     cstm_status st = cstm_guard([&] {
         CSTM_REQUIRE(ctx && g && out, CSTM_EINVAL, "NULL argument");
@@ -201,6 +217,7 @@ extern "C" cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, ui
         srv->g = g;
         srv->budget = mem_budget;
         srv->max_batch = max_batch;
+        srv->batch_wait_us = batch_wait_us < 0 ? 0 : batch_wait_us;
         srv->t0 = Clock::now();
         for (int i = 0; i < builders + lanes; ++i) {
             hipStream_t s = nullptr;
@@ -219,7 +236,7 @@ extern "C" cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, ui
 }
 
 extern "C" cstm_status cstm_server_submit(cstm_server* srv, int32_t k, const int32_t* qlabel, int32_t m_q,
-                                          const int32_t* qedges, uint64_t* ticket) {
+                                          const int32_t* qedges, uint64_t limit, uint64_t* ticket) {
     return cstm_guard([&] {
         CSTM_REQUIRE(srv && ticket, CSTM_EINVAL, "NULL argument");
         CSTM_REQUIRE(k >= 1 && k <= CSTM_MAX_K && qlabel, CSTM_EINVAL, "query size k must be in 1..32");
@@ -229,6 +246,7 @@ extern "C" cstm_status cstm_server_submit(cstm_server* srv, int32_t k, const int
         r->k = k;
         for (int u = 0; u < k; ++u) r->qlabel[u] = qlabel[u];
         r->qedges.assign(qedges, qedges + 2 * (size_t)m_q);
+        r->limit = limit;
         std::lock_guard<std::mutex> lk(srv->mu);
         CSTM_REQUIRE(!srv->closing, CSTM_EINVAL, "server is shutting down");
         r->id = srv->next_id++;

@@ -156,14 +156,14 @@ def load_library():
         "cstm_cst_candidates": (st, [P, I32, P, I64, ctypes.POINTER(I64)]),
         "cstm_enumerate": (st, [P, ctypes.c_int, U64, P, U64, ctypes.POINTER(U64), ctypes.POINTER(U64),
                                 ctypes.c_double, P]),
-        "cstm_batch_enumerate": (st, [P, I32, P, P, P]),
+        "cstm_batch_enumerate": (st, [P, I32, P, P, P, P]),
         "cstm_cst_times": (st, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
         "cstm_cst_free": (None, [P]),
         "cstm_ctx_last_enum_stats": (st, [P, ctypes.POINTER(cstm_enum_stats)]),
         "cstm_cst_estimate": (st, [P, I32, P, I32, P, ctypes.POINTER(U64)]),
-        "cstm_server_create": (st, [P, P, U64, I32, I32, I32, ctypes.POINTER(P)]),
-        "cstm_server_submit": (st, [P, I32, P, I32, P, ctypes.POINTER(U64)]),
+        "cstm_server_create": (st, [P, P, U64, I32, I32, I32, I32, ctypes.POINTER(P)]),
+        "cstm_server_submit": (st, [P, I32, P, I32, P, U64, ctypes.POINTER(U64)]),
         "cstm_server_poll": (st, [P, U64, ctypes.POINTER(cstm_request_result)]),
         "cstm_server_wait": (st, [P, U64, ctypes.c_double, ctypes.POINTER(cstm_request_result)]),
         "cstm_server_get_stats": (st, [P, ctypes.POINTER(cstm_server_stats)]),
@@ -416,21 +416,22 @@ class Server:
     """
 
     def __init__(self, ctx: Context, graph: "Graph", mem_budget: int = 64 << 30, lanes: int = 2,
-                 builders: int = 4, max_batch: int = 256):
+                 builders: int = 4, max_batch: int = 256, batch_wait_us: int = 0):
         self.ctx = ctx
         self.graph = graph
         h = ctypes.c_void_p()
         _check(load_library().cstm_server_create(ctx.handle, graph.handle, int(mem_budget), int(lanes),
-                                                 int(builders), int(max_batch), ctypes.byref(h)))
+                                                 int(builders), int(max_batch), int(batch_wait_us),
+                                                 ctypes.byref(h)))
         self.handle = h
         ctx._children.add(self)
 
-    def submit(self, qlabel, qedges) -> int:
+    def submit(self, qlabel, qedges, limit: int = 0) -> int:
         ql = np.ascontiguousarray(qlabel, dtype=np.int32)
         qe = np.ascontiguousarray(np.asarray(qedges, dtype=np.int32).reshape(-1, 2))
         t = ctypes.c_uint64()
         _check(load_library().cstm_server_submit(self.handle, int(ql.shape[0]), ql.ctypes.data, int(qe.shape[0]),
-                                                 qe.ctypes.data if qe.size else None, ctypes.byref(t)))
+                                                 qe.ctypes.data if qe.size else None, int(limit), ctypes.byref(t)))
         return t.value
 
     @staticmethod
@@ -471,12 +472,18 @@ class Server:
             pass
 
 
-def batch_count(ctx: Context, csts: list, stream=None) -> list[int]:
-    """``cstm_batch_enumerate``: counts of many partitioned CSTs from one persistent launch."""
+def batch_count(ctx: Context, csts: list, stream=None, limits=None) -> list[int]:
+    """``cstm_batch_enumerate``: counts of many CSTs from one persistent launch.
+
+    ``limits`` (optional, one per CST, 0 = all): each count is min(total, limit)."""
     n = len(csts)
     arr = (ctypes.c_void_p * max(n, 1))(*[c.handle.value for c in csts])
     out = (ctypes.c_uint64 * max(n, 1))()
-    _check(load_library().cstm_batch_enumerate(ctx.handle, n, arr, out, _stream_ptr(stream)))
+    lim = None
+    if limits is not None:
+        assert len(limits) == n
+        lim = (ctypes.c_uint64 * max(n, 1))(*[int(x) for x in limits])
+    _check(load_library().cstm_batch_enumerate(ctx.handle, n, arr, lim, out, _stream_ptr(stream)))
     return [int(out[i]) for i in range(n)]
 
 

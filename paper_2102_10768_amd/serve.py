@@ -92,8 +92,8 @@ class CstmBackend:
     def build(self, q, stream):
         return self._cstm.CST(self.ctx, self.graph, q.qlabel, q.qedges, stream=stream)
 
-    def count_batch(self, handles, stream):
-        return self._cstm.batch_count(self.ctx, handles, stream=stream)
+    def count_batch(self, handles, stream, limits=None):
+        return self._cstm.batch_count(self.ctx, handles, stream=stream, limits=limits)
 
     def release(self, handle):
         handle.close()
@@ -263,10 +263,11 @@ class Server:
         return not self._pending and all(r.t_built is not None or r.done for r in self.requests)
 
 
-def run_sequential(backend, arrivals, queries, *, clock=time.perf_counter):
+def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):
     """Plain form: one request at a time in arrival order, build then count on one stream.
 
-    ``arrivals`` are offsets in seconds from the start; returns the requests."""
+    ``arrivals`` are offsets in seconds from the start; ``limit`` > 0 asks for
+    min(total, limit); returns the requests."""
     stream = backend.new_stream()
     start = clock()
     out = []
@@ -279,7 +280,7 @@ def run_sequential(backend, arrivals, queries, *, clock=time.perf_counter):
         h = backend.build(q, stream)
         r.t_built = r.t_launch = clock()
         try:
-            r.count = int(backend.count_batch([h], stream)[0])
+            r.count = int(backend.count_batch([h], stream, [limit] if limit else None)[0])
         except Exception as e:
             r.error = f"enumeration failed: {e}"
         finally:
@@ -305,17 +306,18 @@ def replay(server: Server, arrivals, queries, *, clock=time.perf_counter):
     return reqs
 
 
-def replay_native(server, arrivals, queries, *, clock=time.perf_counter):
+def replay_native(server, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):
     """Submit ``queries[i]`` to a ``cstm.Server`` at ``arrivals[i]`` seconds after
-    the start, wait for every result, and return them as ``Request`` records
-    timed on the server's own clock (submission to result)."""
+    the start (each with the result limit ``limit``, 0 = all), wait for every
+    result, and return them as ``Request`` records timed on the server's own
+    clock (submission to result)."""
     start = clock()
     tickets = []
     for t, q in zip(arrivals, queries):
         now = clock() - start
         if now < t:
             time.sleep(t - now)
-        tickets.append((server.submit(q.qlabel, q.qedges), q))
+        tickets.append((server.submit(q.qlabel, q.qedges, limit), q))
     out = []
     for rid, (tk, q) in enumerate(tickets):
         res = server.wait(tk)

@@ -37,10 +37,12 @@ RMAT_22 = {
 SERVE_16M = {
     "name": "c4",
     "title": "Chung-Lu 16M vertices, 256M edges, gamma 2.1, 100 Zipf(0.8) labels; "
-             "screened pool of random-walk queries of 4..24 vertices, Poisson arrivals",
+             "screened pool of random-walk queries of 4..24 vertices, results limited to 10^6, Poisson arrivals",
     "graph": {"kind": "chung_lu", "n": 16_000_000, "m": 256_000_000, "gamma": 2.1, "seed": 14,
               "labels": {"kind": "zipf", "L": 100, "s": 0.8}},
-    "queries": {"k_min": 4, "k_max": 24, "count": 200, "seed": 24},
+    # each request asks for min(#embeddings, limit): on this graph almost every
+    # random-walk query has far more embeddings than any search can visit
+    "queries": {"k_min": 4, "k_max": 24, "count": 200, "seed": 24, "limit": 1_000_000},
     # request streams: 2,000 arrivals per rate, one seed per rate; admission budget
     "serve": {"rates": [50, 200, 800], "arrivals": 2000, "seeds": [201, 202, 203], "mem_budget_gb": 64},
 }

@@ -134,14 +134,17 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
 
 
 def make_batch(w: dict, budget: int, max_draws: int, threads: int):
-    """Batch workload: query sizes uniform in [k_min, k_max]; each draw is kept when
-    the oracle finishes it within the work budget (the same deterministic screen)."""
+    """Batch / serving workload: query sizes uniform in [k_min, k_max]; each draw
+    is kept when the oracle finishes it within the work budget (the same
+    deterministic screen).  With a result limit L in the recipe, the stored
+    count is min(#embeddings, L) and the oracle may stop once it found L."""
     g = make_graph(w["graph"])
     print("graph", g.summary(), flush=True)
     lcol = oracle.label_grouped_col(g)
     spec = w["queries"]
     rng = _rng(spec["seed"], STREAM_QUERIES)
     want = int(spec["count"])
+    limit = int(spec.get("limit", 0))
     out = []
     stats = {"draws": 0, "over_budget": 0}
     t_start = time.time()
@@ -152,7 +155,7 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
         q = random_walk_query(g, k, rng)
         stats["draws"] += 1
         t = time.time()
-        r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol)
+        r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol, limit=limit)
         dt = time.time() - t
         if (draw + 1) % 250 == 0:
             print(f"{draw + 1} draws, {len(out)} kept ({time.time() - t_start:.0f}s)", flush=True)
@@ -162,6 +165,8 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
         d = q.to_dict()
         d.update(draw=draw, qid=len(out), count=r.count, nodes=r.nodes, oracle_s=round(dt, 4),
                  expected_from="oracle")
+        if limit:
+            d["limit"] = limit
         out.append(d)
         if len(out) % 50 == 0:
             print(f"{len(out)}/{want} after {draw + 1} draws ({time.time() - t_start:.0f}s)", flush=True)
@@ -169,7 +174,8 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
     write(w["name"], {
         "workload": w,
         "graph_summary": g.summary(),
-        "screen": {"rule": "oracle (label-grouped rows) finishes within node_budget work units",
+        "screen": {"rule": "oracle (label-grouped rows) finishes within node_budget work units"
+                           + (f" or finds {limit} embeddings (stored count = min(total, {limit}))" if limit else ""),
                    "node_budget": budget, "sizes_kept": {str(k): sum(1 for d in out if len(d["qlabel"]) == k)
                                                          for k in range(int(spec["k_min"]), int(spec["k_max"]) + 1)},
                    "max_draws": max_draws, **stats, "short": want - len(out)},

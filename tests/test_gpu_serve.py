@@ -63,8 +63,9 @@ def test_served_results_equal_results_alone(name, n_req, qps):
     assert srv.peak_bytes <= 8 << 30
 
 
-@pytest.mark.parametrize("name,n_req,qps", [("c1", 200, 4000.0), ("c2", 24, 40.0)])
-def test_native_server_results_equal_results_alone(name, n_req, qps):
+@pytest.mark.parametrize("name,n_req,qps,wait_us", [("c1", 200, 4000.0, 0), ("c1", 200, 4000.0, 2000),
+                                                     ("c2", 24, 40.0, 2000)])
+def test_native_server_results_equal_results_alone(name, n_req, qps, wait_us):
     """cstm_server_*: every served count equals the stored count of the query alone."""
     from paper_2102_10768_amd import cstm, serve
 
@@ -80,7 +81,7 @@ def test_native_server_results_equal_results_alone(name, n_req, qps):
     else:
         picks = rng.integers(0, len(pool), size=n_req)
     arr = serve.poisson_arrivals(n_req, qps, 206)
-    with cstm.Server(c, G, mem_budget=8 << 30, lanes=2, builders=4) as srv:
+    with cstm.Server(c, G, mem_budget=8 << 30, lanes=2, builders=4, batch_wait_us=wait_us) as srv:
         reqs = serve.replay_native(srv, arr, [pool[int(p)] for p in picks])
         st = srv.stats()
         # a malformed query finishes with its own error status, others are unaffected
@@ -108,3 +109,23 @@ def test_native_server_refuses_a_request_larger_than_the_budget():
         t = srv.submit(q.qlabel, q.qedges)
         res = srv.wait(t)
     assert res["status"] == cstm.ENOMEM and res["count"] == 0
+
+
+def test_native_server_with_result_limits():
+    """Served requests with a result limit return min(total, limit)."""
+    from paper_2102_10768_amd import cstm, serve
+
+    W = _load("c2")
+    g = make_graph(W["workload"]["graph"])
+    G = gpu_graph(g, "hbm")
+    pool = [Query.from_dict(d) for d in W["queries"]]
+    expected = [int(d["count"]) for d in W["queries"]]
+    rng = np.random.Generator(np.random.PCG64(207))
+    picks = rng.integers(0, len(pool), size=60)
+    arr = serve.poisson_arrivals(len(picks), 400.0, 208)
+    lim = 10**7
+    with cstm.Server(ctx("hbm"), G, mem_budget=8 << 30, lanes=2, builders=4, batch_wait_us=2000) as srv:
+        reqs = serve.replay_native(srv, arr, [pool[int(p)] for p in picks], limit=lim)
+    say(f"limited: {serve.summarize(reqs)}")
+    for r, p in zip(reqs, picks):
+        assert r.error is None and r.count == min(expected[int(p)], lim)

@@ -278,3 +278,20 @@ def test_per_call_deadline():
     assert ei.value.status == cstm.ETIMEOUT
     assert c.count(deadline_s=30.0) == heavy["count"]
     c.close()
+
+
+def test_batched_limits_give_min_of_total_and_limit():
+    """Per-query limits in one persistent launch: each count is min(total, limit)."""
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c2")
+    g, G = _graph("c2", W, "hbm")
+    ds = W["queries"][:12]
+    qs = [Query.from_dict(d) for d in ds]
+    csts = [cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges) for q in qs]
+    totals = [d["count"] for d in ds]
+    limits = [0, 1, 10**6, totals[3], totals[4] + 1, 10**9, 7, 0, 10**8, 12345, totals[10] // 2, 0]
+    got = cstm.batch_count(ctx("hbm"), csts, limits=limits)
+    for c in csts:
+        c.close()
+    assert got == [t if lim == 0 else min(t, lim) for t, lim in zip(totals, limits)]

@@ -265,6 +265,31 @@ def test_label_grouped_rows_are_regrouped_rows_and_change_no_result():
         assert b.nodes <= a.nodes
 
 
+@pytest.mark.parametrize("seed", range(20))
+def test_count_limit_is_min_of_total_and_limit(seed):
+    rng = np.random.default_rng(7000 + seed)
+    g = random_tiny_graph(rng)
+    q = random_connected_query(rng, L=int(g.label.max()) + 1)
+    total = len(bruteforce.embeddings(g, q))
+    for lim in sorted({1, max(1, total // 2), total, total + 1, 10 * total + 3}):
+        for threads in (1, 3):
+            r = oracle.match(g, q, limit=lim, threads=threads)
+            assert r.status == oracle.OK
+            assert r.count == min(total, lim)
+
+
+def test_count_limit_stops_early_on_a_large_count():
+    g = cf.complete(60)
+    q = cf.clique_query([0] * 4)
+    full = oracle.match(g, q)
+    assert full.count == cf.clique_host_count(60, 4)
+    r = oracle.match(g, q, limit=1000, threads=4)
+    assert r.status == oracle.OK and r.count == 1000
+    assert r.nodes < full.nodes // 10
+    with pytest.raises(ValueError):
+        oracle.match(g, q, limit=10, list_rows=True)
+
+
 def test_node_budget_is_deterministic_and_reports_timeout():
     g = _c1_graph()
     q = query_set(g, [6], 41)[0]

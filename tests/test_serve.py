@@ -47,7 +47,7 @@ class FakeBackend:
         time.sleep(0.0005)
         return q
 
-    def count_batch(self, handles, stream):
+    def count_batch(self, handles, stream, limits=None):
         self.launch_sizes.append(len(handles))
         time.sleep(max(h.seconds for h in handles))
         if any(h.count < 0 for h in handles):
