@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=0, help="requests per rate for --serve (default: the workload's)")
     ap.add_argument("--mem-budget-gb", type=float, default=0.0, help="admission budget for --serve (default: the workload's)")
     ap.add_argument("--batch-wait-us", type=int, default=2000, help="--serve: lanes under load wait this long for more CSTs")
+    ap.add_argument("--lanes", type=int, default=2, help="--serve: enumeration lanes (streams)")
+    ap.add_argument("--builders", type=int, default=2, help="--serve: CST builder threads (streams)")
+    ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
@@ -292,10 +295,12 @@ def serve_main(a, W, g, queries, expected):
     if len(seeds) < len(rates):
         seeds = [201 + i for i in range(len(rates))]
     budget = int((a.mem_budget_gb or spec.get("mem_budget_gb", 64)) * (1 << 30))
+    # each request asks for min(total, limit) when the workload sets a result limit
+    limit = int(W["workload"]["queries"].get("limit", 0))
     # warm-up: every query once, alone (also the check that the pool's counts hold)
     for q, e in zip(queries, expected):
         c = cstm.CST(ctx, G, q.qlabel, q.qedges)
-        n = c.count()
+        n = c.count(limit=limit)
         c.close()
         if n != e:
             print(f"COUNT MISMATCH in warm-up: {n} != {e}", file=sys.stderr)
@@ -309,15 +314,16 @@ def serve_main(a, W, g, queries, expected):
         picks = np.random.Generator(np.random.PCG64(301 + i)).integers(0, len(queries), size=n)
         qs = [queries[int(p)] for p in picks]
         want = [expected[int(p)] for p in picks]
-        with cstm.Server(ctx, G, mem_budget=budget, lanes=2, builders=4, batch_wait_us=a.batch_wait_us) as srv:
-            served = serve.replay_native(srv, arr, qs)
+        with cstm.Server(ctx, G, mem_budget=budget, lanes=a.lanes, builders=a.builders,
+                         batch_wait_us=a.batch_wait_us) as srv:
+            served = serve.replay_native(srv, arr, qs, limit=limit)
             sst = srv.stats()
         s_srv = serve.summarize(served)
         s_srv["peak_charged_bytes"] = sst["peak_bytes"]
         s_srv["lane_overlap"] = sst["max_overlap"]
         s_srv["launches"] = sst["launches"]
         print(f"{qps} QPS served: {s_srv}", file=sys.stderr, flush=True)
-        plain = serve.run_sequential(backend, arr, qs)
+        plain = served if a.skip_plain else serve.run_sequential(backend, arr, qs, limit=limit)
         s_pl = serve.summarize(plain)
         print(f"{qps} QPS plain: {s_pl}", file=sys.stderr, flush=True)
         bad = sum(r.count != w for r, w in zip(served, want)) + sum(r.count != w for r, w in zip(plain, want))
@@ -342,11 +348,12 @@ def serve_main(a, W, g, queries, expected):
         "config": {
             "workload": W["workload"]["title"],
             "name": a.workload,
-            "form": "served (cstm_server): Poisson arrivals, admission by CST footprint bound, 4 CST builder "
-                    "threads, 2 enumeration lanes with batched persistent launches (batching window under load); "
-                    "value is at the highest rate",
+            "form": f"served (cstm_server): Poisson arrivals, admission by CST footprint bound, {a.builders} CST "
+                    f"builder threads, {a.lanes} enumeration lanes with batched persistent launches (batching window "
+                    "under load); value is at the highest rate",
             "batch_wait_us": a.batch_wait_us,
             "query_pool": len(queries),
+            "result_limit": limit,
             "mem_budget_bytes": budget,
         },
         "parity": {"checked": 2 * sum(r["requests"] for r in rows), "mismatches": mismatches},

@@ -267,7 +267,10 @@ cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* cst
  * its own stream.  Several lanes run launches at the same time.  A request's
  * count does not depend on which requests share its launch.  The server is
  * thread-safe; it uses the context's tuning (deadline_ms applies per launch).
- * Zero or negative lanes / builders / max_batch take the defaults 2 / 4 / 256.
+ * Zero or negative lanes / builders / max_batch take the defaults 2 / 2 / 256
+ * (lanes + builders streams: HIP maps a process's streams onto a few
+ * hardware queues, 4 by default, and streams sharing one queue run in
+ * order, so a build queued behind a long enumeration launch would wait).
  * batch_wait_us: when a lane finds built CSTs while another lane is already
  * running a launch (the server is under load) and more requests are on their
  * way, it waits up to this long for more to join its launch; an idle server

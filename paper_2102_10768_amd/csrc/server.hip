@@ -207,7 +207,7 @@ extern "C" cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, ui
         *out = nullptr;
         CSTM_REQUIRE(g->ctx == ctx, CSTM_EINVAL, "graph belongs to another context");
         if (lanes <= 0) lanes = 2;
-        if (builders <= 0) builders = 4;
+        if (builders <= 0) builders = 2;
         if (max_batch <= 0) max_batch = 256;
         CSTM_REQUIRE(lanes <= 16 && builders <= 64, CSTM_EINVAL, "at most 16 lanes and 64 builders");
         CSTM_REQUIRE(mem_budget > 0, CSTM_EINVAL, "memory budget must be positive");

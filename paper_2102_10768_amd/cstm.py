@@ -416,7 +416,7 @@ class Server:
     """
 
     def __init__(self, ctx: Context, graph: "Graph", mem_budget: int = 64 << 30, lanes: int = 2,
-                 builders: int = 4, max_batch: int = 256, batch_wait_us: int = 0):
+                 builders: int = 2, max_batch: int = 256, batch_wait_us: int = 0):
         self.ctx = ctx
         self.graph = graph
         h = ctypes.c_void_p()

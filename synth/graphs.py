@@ -65,7 +65,7 @@ class Graph:
         }
 
 
-def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, log=None) -> tuple[np.ndarray, np.ndarray]:
     """Simple undirected CSR from an endpoint list (loops dropped, duplicates merged)."""
     a = np.asarray(a, dtype=np.int64)
     b = np.asarray(b, dtype=np.int64)
@@ -74,6 +74,8 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray) -> tuple[np.ndarray, np
     lo = np.minimum(a, b)
     hi = np.maximum(a, b)
     key = np.unique(lo * n + hi)
+    if log:
+        log(f"csr: {key.shape[0]} distinct edges")
     lo = key // n
     hi = key % n
     del key
@@ -83,6 +85,8 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray) -> tuple[np.ndarray, np
     key2 = src * n + dst
     del src, dst
     key2.sort()
+    if log:
+        log("csr: adjacency sorted")
     src = key2 // n
     col = (key2 % n).astype(np.int32)
     del key2
@@ -163,6 +167,8 @@ def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
         batch = int(need * 1.3) + 4096
         a = endpoints(batch)
         b = endpoints(batch)
+        if log:
+            log(f"chung_lu: {2 * batch} endpoints drawn")
         keep = a != b
         a, b = a[keep].astype(np.int64), b[keep].astype(np.int64)
         key = np.minimum(a, b) * n + np.maximum(a, b)
@@ -170,6 +176,8 @@ def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
         all_keys = np.concatenate([all_keys, key])
         del key
         # keep the distinct pairs in the order they were first drawn
+        if log:
+            log(f"chung_lu: deduplicating {all_keys.shape[0]} pairs")
         _, first = np.unique(all_keys, return_index=True)
         first.sort()
         if log:
@@ -183,7 +191,7 @@ def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
     hi = all_keys % n
     del all_keys
     perm = _rng(seed, STREAM_PERM).permutation(n).astype(np.int64)
-    out = csr_from_edges(n, perm[lo], perm[hi])
+    out = csr_from_edges(n, perm[lo], perm[hi], log=log)
     if log:
         log("chung_lu: CSR built")
     return out
