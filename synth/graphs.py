@@ -65,6 +65,23 @@ class Graph:
         }
 
 
+def _sorted_unique(keys: np.ndarray, bound: int, log=None) -> np.ndarray:
+    """np.unique(keys) for non-negative keys below ``bound``; very large arrays
+    are split into 64 ranges of the key space, each sorted on its own, so the
+    work reports progress and needs less temporary memory (same result)."""
+    if keys.shape[0] < (1 << 27):
+        return np.unique(keys)
+    shift = max(0, int(bound - 1).bit_length() - 6)
+    parts = []
+    for b in range(64):
+        part = np.unique(keys[(keys >> shift) == b])
+        parts.append(part)
+        if log and b % 8 == 7:
+            log(f"sorted {b + 1}/64 key ranges")
+    return np.concatenate(parts)
+
+
+
 def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, log=None) -> tuple[np.ndarray, np.ndarray]:
     """Simple undirected CSR from an endpoint list (loops dropped, duplicates merged)."""
     a = np.asarray(a, dtype=np.int64)
@@ -73,7 +90,7 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, log=None) -> tuple[np.n
     a, b = a[keep], b[keep]
     lo = np.minimum(a, b)
     hi = np.maximum(a, b)
-    key = np.unique(lo * n + hi)
+    key = _sorted_unique(lo * n + hi, n * n, log)
     if log:
         log(f"csr: {key.shape[0]} distinct edges")
     lo = key // n
@@ -84,7 +101,7 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, log=None) -> tuple[np.n
     del lo, hi
     key2 = src * n + dst
     del src, dst
-    key2.sort()
+    key2 = _sorted_unique(key2, n * n, log)  # all distinct: a plain sort
     if log:
         log("csr: adjacency sorted")
     src = key2 // n
@@ -197,7 +214,7 @@ def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
     return out
 
 
-def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int, chunk: int = 1 << 24):
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int, chunk: int = 1 << 24, log=None):
     """R-MAT (Graph500 style): 2^scale vertices, edge_factor * 2^scale samples.
 
     Each sample picks one quadrant per bit level with probabilities a, b, c and
@@ -226,9 +243,12 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int, 
         hi = np.maximum(src[keep], dst[keep])
         keys.append(np.unique(lo * n + hi))
         done += cnt
-    key = np.unique(np.concatenate(keys))
+        if log and (done // cnt) % 8 == 0:
+            log(f"rmat: {done} of {samples} samples")
+    key = _sorted_unique(np.concatenate(keys), n * n, log)
+    del keys
     perm = _rng(seed, STREAM_PERM).permutation(n).astype(np.int64)
-    return csr_from_edges(n, perm[key // n], perm[key % n])
+    return csr_from_edges(n, perm[key // n], perm[key % n], log=log)
 
 
 def uniform_labels(n: int, num_labels: int, seed: int) -> np.ndarray:
@@ -268,6 +288,7 @@ def make_graph(spec: dict, log=None) -> Graph:
             float(spec.get("b", 0.19)),
             float(spec.get("c", 0.19)),
             seed,
+            log=log,
         )
     else:
         raise ValueError(f"unknown graph kind {kind!r}")
