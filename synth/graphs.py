@@ -173,9 +173,11 @@ def chung_lu(n: int, m_target: int, gamma: float, seed: int, log=None):
 
     def endpoints(count):
         out = np.empty(count, dtype=itype)
-        for s0 in range(0, count, chunk):
+        for i, s0 in enumerate(range(0, count, chunk)):
             s1 = min(count, s0 + chunk)
             out[s0:s1] = np.minimum(np.searchsorted(cdf, rng.random(s1 - s0), side="right"), n - 1)
+            if log and i % 4 == 3:
+                log(f"chung_lu: {s1} of {count} endpoints")
         return out
 
     all_keys = np.zeros(0, dtype=np.int64)
