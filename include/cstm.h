@@ -285,6 +285,9 @@ typedef struct {
                             launch                                                   */
     uint64_t count;      /* number of embeddings (status CSTM_OK)                    */
     double submit_s;     /* server clock, seconds since creation, at submission     */
+    double admit_s;      /* ... when it was admitted and its build began            */
+    double built_s;      /* ... when its CST was built                               */
+    double launch_s;     /* ... when its enumeration launch began                    */
     double done_s;       /* ... when the result became available                    */
     int32_t batch_size;  /* requests that shared its enumeration launch             */
     int32_t lane;        /* the lane that ran it                                    */

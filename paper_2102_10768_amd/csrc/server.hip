@@ -112,6 +112,7 @@ struct cstm_server {
                         in_use += r->charge;
                         if (in_use > st.peak_bytes) st.peak_bytes = in_use;
                         unbuilt++;
+                        r->res.admit_s = now();
                         break;
                     }
                     cv.wait(lk);
@@ -136,6 +137,7 @@ struct cstm_server {
             unbuilt--;
             r->cst = c;
             r->built = true;
+            r->res.built_s = now();
             ready.push_back(r);
             cv.notify_all();
         }
@@ -172,6 +174,7 @@ struct cstm_server {
                 st.launches++;
                 st.batched += batch.size();
             }
+            const double t_launch = now();
             csts.clear();
             limits.clear();
             bool any_limit = false;
@@ -181,6 +184,7 @@ struct cstm_server {
                 any_limit |= r->limit != 0;
                 r->res.batch_size = (int32_t)batch.size();
                 r->res.lane = lane;
+                r->res.launch_s = t_launch;
             }
             counts.assign(batch.size(), 0);
             cstm_status e = cstm_guard([&] {

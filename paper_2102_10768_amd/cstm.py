@@ -71,6 +71,9 @@ class cstm_request_result(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("count", ctypes.c_uint64),
         ("submit_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("built_s", ctypes.c_double),
+        ("launch_s", ctypes.c_double),
         ("done_s", ctypes.c_double),
         ("batch_size", ctypes.c_int32),
         ("lane", ctypes.c_int32),

@@ -322,6 +322,9 @@ def replay_native(server, arrivals, queries, *, limit: int = 0, clock=time.perf_
     for rid, (tk, q) in enumerate(tickets):
         res = server.wait(tk)
         r = Request(rid, q, res["submit_s"])
+        r.t_admit = res["admit_s"]
+        r.t_built = res["built_s"]
+        r.t_launch = res["launch_s"]
         r.t_done = res["done_s"]
         r.batch_size = res["batch_size"]
         r.lane = res["lane"]
@@ -353,12 +356,19 @@ def summarize(reqs) -> dict:
     lat = [r.latency for r in ok]
     span = (max(r.t_done for r in reqs) - min(r.t_arrival for r in reqs)) if reqs else 0.0
     total = sum(r.count for r in ok)
+    def mean_ms(a, b):
+        xs = [getattr(r, b) - getattr(r, a) for r in ok if getattr(r, a) is not None and getattr(r, b) is not None]
+        return 1e3 * float(np.mean(xs)) if xs else None
+
     return {
         "requests": len(reqs),
         "completed": len(ok),
         "errors": len(reqs) - len(ok),
         "p50_ms": 1e3 * nearest_rank(lat, 50),
         "p99_ms": 1e3 * nearest_rank(lat, 99),
+        # mean time per stage: waiting for admission, building, waiting for a lane, enumerating
+        "mean_ms": {"admit_wait": mean_ms("t_arrival", "t_admit"), "build": mean_ms("t_admit", "t_built"),
+                    "launch_wait": mean_ms("t_built", "t_launch"), "enumerate": mean_ms("t_launch", "t_done")},
         "mean_batch": float(np.mean([r.batch_size for r in ok])) if ok else 0.0,
         "embeddings": total,
         "seconds": span,
