@@ -219,9 +219,12 @@ cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const int32_t* qla
  * on-chip image is at most budget_bytes and its longest list at most
  * max_list_len (0 = no limit); budget_bytes = 0 takes the context's tuning.
  * Partitions are independent and together hold every embedding exactly once.
+ * max_total_bytes (0 = no limit): give up with CSTM_ENOMEM, leaving the CST
+ * unpartitioned, once the images together would exceed it (on hub-heavy
+ * graphs the images can replicate the CST many times over).
  * *n_parts_out (may be NULL) receives the number of partitions. */
 cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max_list_len,
-                               int64_t* n_parts_out);
+                               uint64_t max_total_bytes, int64_t* n_parts_out);
 
 cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
 

@@ -648,22 +648,27 @@ bool cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list, uint64_t
 }
 
 extern "C" cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max_list_len,
-                                          int64_t* n_parts_out) {
+                                          uint64_t max_total_bytes, int64_t* n_parts_out) {
     return cstm_guard([&] {
         CSTM_REQUIRE(cst, CSTM_EINVAL, "NULL cst");
         HIP_TRY(hipSetDevice(cst->ctx->device));
-        hipEvent_t a, b;
-        HIP_TRY(hipEventCreate(&a));
-        HIP_TRY(hipEventCreate(&b));
-        HIP_TRY(hipEventRecord(a, cst->stream));
-        cstm_partition_run(cst, budget_bytes, max_list_len);
-        HIP_TRY(hipEventRecord(b, cst->stream));
-        HIP_TRY(hipEventSynchronize(b));
+        struct Events {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~Events() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev;
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        HIP_TRY(hipEventRecord(ev.a, cst->stream));
+        const bool done = cstm_partition_run(cst, budget_bytes, max_list_len, max_total_bytes);
+        HIP_TRY(hipEventRecord(ev.b, cst->stream));
+        HIP_TRY(hipEventSynchronize(ev.b));
         float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, a, b));
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
         cst->t_part = ms;
-        if (n_parts_out) *n_parts_out = cst->n_parts;
+        if (n_parts_out) *n_parts_out = done ? cst->n_parts : 0;
+        CSTM_REQUIRE(done, CSTM_ENOMEM, "partition images would exceed max_total_bytes; the CST stays unpartitioned");
     });
 }

@@ -154,7 +154,7 @@ def load_library():
         "cstm_graph_free": (None, [P]),
         "cstm_graph_info": (st, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I64)]),
         "cstm_cst_build": (st, [P, P, I32, P, I32, P, P, ctypes.POINTER(P)]),
-        "cstm_cst_partition": (st, [P, U64, I32, ctypes.POINTER(I64)]),
+        "cstm_cst_partition": (st, [P, U64, I32, U64, ctypes.POINTER(I64)]),
         "cstm_cst_info_get": (st, [P, ctypes.POINTER(cstm_cst_info)]),
         "cstm_cst_candidates": (st, [P, I32, P, I64, ctypes.POINTER(I64)]),
         "cstm_enumerate": (st, [P, ctypes.c_int, U64, P, U64, ctypes.POINTER(U64), ctypes.POINTER(U64),
@@ -346,9 +346,12 @@ class CST:
         self.handle = h
         ctx._children.add(self)
 
-    def partition(self, budget_bytes: int = 0, max_list_len: int = 0) -> int:
+    def partition(self, budget_bytes: int = 0, max_list_len: int = 0, max_total_bytes: int = 0) -> int:
+        """Algorithm 2; returns the number of partitions.  Raises ``CstmError``
+        (ENOMEM) when the images would exceed ``max_total_bytes`` (0: no limit)."""
         n = ctypes.c_int64()
-        _check(load_library().cstm_cst_partition(self.handle, int(budget_bytes), int(max_list_len), ctypes.byref(n)))
+        _check(load_library().cstm_cst_partition(self.handle, int(budget_bytes), int(max_list_len),
+                                                 int(max_total_bytes), ctypes.byref(n)))
         return n.value
 
     def info(self) -> dict:

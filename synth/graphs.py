@@ -270,7 +270,7 @@ def make_graph(spec: dict, log=None) -> Graph:
     """Build a graph from a plain dict spec.
 
     ``{"kind": "er", "n", "p"}``, ``{"kind": "chung_lu", "n", "m", "gamma"}`` or
-    ``{"kind": "rmat", "scale", "edge_factor", "a", "b", "c"}``, each with
+    ``{"kind": "rmat" | "rmat_native", "scale", "edge_factor", "a", "b", "c"}``, each with
     ``"seed"`` and ``"labels": {"kind": "uniform"|"zipf", "L", ["s"]}``.
     """
     kind = spec["kind"]
@@ -281,6 +281,17 @@ def make_graph(spec: dict, log=None) -> Graph:
     elif kind == "chung_lu":
         n = int(spec["n"])
         row_ptr, col = chung_lu(n, int(spec["m"]), float(spec["gamma"]), seed, log=log)
+    elif kind == "rmat_native":
+        from . import native
+
+        n = 1 << int(spec["scale"])
+        if log:
+            log(f"rmat (native): scale {spec['scale']}")
+        row_ptr, col = native.rmat_csr(int(spec["scale"]), int(spec.get("edge_factor", 16)),
+                                       float(spec.get("a", 0.57)), float(spec.get("b", 0.19)),
+                                       float(spec.get("c", 0.19)), seed)
+        if log:
+            log(f"rmat (native): {col.shape[0] // 2} edges")
     elif kind == "rmat":
         n = 1 << int(spec["scale"])
         row_ptr, col = rmat(

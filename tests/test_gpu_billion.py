@@ -1,0 +1,134 @@
+"""Billion-edge configuration: R-MAT scale 26 (about 1e9 undirected edges,
+128 labels), 200 random-walk queries of 12..32 vertices, each asking for
+min(#embeddings, 10^6).
+
+One session generates the graph (native generator), builds every CST, reports
+how many partitions Algorithm 2 makes at the LDS budget (or that the images
+would replicate the CST beyond 16 times its size), counts all queries in one
+persistent launch, and checks the counts against the oracle on the host for
+the queries it finishes within its per-query time limit (fastest GPU queries
+first, as long as the session's oracle time lasts).
+
+Generating the graph takes minutes and about 30 GB of host memory, so the test
+runs only when CSTM_BILLION=1 is set.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(os.environ.get("CSTM_BILLION") != "1",
+                                                  reason="set CSTM_BILLION=1 to run the billion-edge session")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_billion_edge_batch_with_oracle_parity():
+    import torch
+
+    import oracle
+    from paper_2102_10768_amd import cstm
+    from synth import make_graph
+    from synth.graphs import _rng
+    from synth.queries import STREAM_QUERIES, random_walk_query
+    from synth.workloads import BILLION
+
+    t0 = time.time()
+    g = make_graph(BILLION["graph"], log=say)
+    say(f"graph: n={g.n} m={g.m} max_degree={int(np.diff(g.row_ptr).max())} ({time.time() - t0:.0f}s)")
+    spec = BILLION["queries"]
+    limit = int(spec["limit"])
+    rng = _rng(spec["seed"], STREAM_QUERIES)
+    qs = []
+    for _ in range(int(spec["count"])):
+        k = int(rng.integers(int(spec["k_min"]), int(spec["k_max"]) + 1))
+        qs.append(random_walk_query(g, k, rng))
+    say(f"{len(qs)} queries drawn")
+
+    ctx = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 0})
+    G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
+                   torch.from_numpy(g.label).cuda())
+    torch.cuda.synchronize()
+    say("graph resident on the device")
+    # groups of queries whose CST bounds fit a device-memory share; each group is
+    # built, partitioned (reported), counted in one persistent launch and freed
+    share = 96 << 30
+    est = [G.estimate_bytes(q.qlabel, q.qedges) for q in qs]
+    groups, cur, cur_b = [], [], 0
+    for i, e in enumerate(est):
+        if cur and cur_b + e > share:
+            groups.append(cur)
+            cur, cur_b = [], 0
+        cur.append(i)
+        cur_b += e
+    groups.append(cur)
+    say(f"{len(groups)} launch groups; largest CST bound {max(est)} bytes")
+    counts = [0] * len(qs)
+    gpu_ms = [0.0] * len(qs)
+    infos = [None] * len(qs)
+    parts = [None] * len(qs)
+    build_s = batch_s = 0.0
+    for grp in groups:
+        t = time.time()
+        csts = [cstm.CST(ctx, G, qs[i].qlabel, qs[i].qedges) for i in grp]
+        build_s += time.time() - t
+        for i, c in zip(grp, csts):
+            infos[i] = c.info()
+            # Algorithm 2 at the context's LDS budget, stopped where images would
+            # replicate the CST beyond 16 times its size (or 4 GB)
+            try:
+                parts[i] = c.partition(0, 0, min(16 * max(infos[i]["bytes"], 4096), 4 << 30))
+            except cstm.CstmError:
+                parts[i] = None
+        cstm.batch_count(ctx, csts, limits=[limit] * len(csts))
+        t = time.perf_counter()
+        got = cstm.batch_count(ctx, csts, limits=[limit] * len(csts))
+        batch_s += time.perf_counter() - t
+        for i, c, n in zip(grp, csts, got):
+            counts[i] = n
+            t = time.perf_counter()
+            assert c.count(limit=limit) == n  # one query per launch agrees with the batch
+            gpu_ms[i] = 1e3 * (time.perf_counter() - t)
+            c.close()
+        say(f"group of {len(grp)}: done")
+    n_ok = sum(p is not None for p in parts)
+    say(f"built in {build_s:.1f}s; partitioned {n_ok} of {len(qs)} within the replication cap; "
+        f"batched launches {batch_s * 1e3:.1f} ms, {sum(counts)} embeddings")
+
+    # oracle parity, fastest GPU queries first, within the session's oracle time
+    order = sorted(range(len(qs)), key=lambda i: gpu_ms[i])
+    checked, inf, oracle_s = 0, 0, 0.0
+    for i in order:
+        if oracle_s > 240.0:
+            break
+        t = time.time()
+        r = oracle.match(g, qs[i], limit=limit, deadline_s=20.0)
+        dt = time.time() - t
+        oracle_s += dt
+        if r.status != oracle.OK:
+            inf += 1
+            continue
+        assert r.count == counts[i], f"query {i}: gpu {counts[i]} oracle {r.count}"
+        checked += 1
+    summary = {
+        "graph": {"n": g.n, "m": g.m, "max_degree": int(np.diff(g.row_ptr).max())},
+        "queries": len(qs), "limit": limit, "build_s": build_s, "launch_groups": len(groups),
+        "partitioned_within_cap": n_ok, "parts": parts,
+        "cst_bytes": [i["bytes"] for i in infos], "cst_bound_bytes": est,
+        "batched_ms": batch_s * 1e3, "embeddings": sum(counts),
+        "per_query_gpu_ms": gpu_ms,
+        "oracle": {"checked": checked, "inf": inf, "seconds": oracle_s, "threads": oracle.num_cores()},
+    }
+    say("SUMMARY " + json.dumps(summary))
+    assert checked > 0
+    G.close()
+    ctx.close()
