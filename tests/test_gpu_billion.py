@@ -2,12 +2,13 @@
 128 labels), 200 random-walk queries of 12..32 vertices, each asking for
 min(#embeddings, 10^6).
 
-One session generates the graph (native generator), builds every CST, reports
-how many partitions Algorithm 2 makes at the LDS budget (or that the images
-would replicate the CST beyond 16 times its size), counts all queries in one
-persistent launch, and checks the counts against the oracle on the host for
-the queries it finishes within its per-query time limit (fastest GPU queries
-first, as long as the session's oracle time lasts).
+One session generates the graph (native generator), builds every CST, tries
+Algorithm 2 at the LDS budget on the first few (reporting the partition count,
+or that the images would replicate the CST beyond 16 times its size), counts
+the queries in persistent launches over groups that fit a device-memory share,
+and checks the counts against the oracle on the host for the queries it
+finishes within its per-query time limit (fastest GPU queries first, as long
+as the session's oracle time lasts).
 
 Generating the graph takes minutes and about 30 GB of host memory, so the test
 runs only when CSTM_BILLION=1 is set.
@@ -77,6 +78,7 @@ def test_billion_edge_batch_with_oracle_parity():
     infos = [None] * len(qs)
     parts = [None] * len(qs)
     build_s = batch_s = 0.0
+    n_partition = int(os.environ.get("CSTM_BILLION_PARTITIONS", "4"))
     for grp in groups:
         csts = []
         for i in grp:
@@ -86,11 +88,10 @@ def test_billion_edge_batch_with_oracle_parity():
             infos[i] = csts[-1].info()
             say(f"query {i} k={qs[i].k}: CST {infos[i]['bytes']} bytes built in {time.time() - t:.2f}s")
         for i, c in zip(grp, csts):
-            # Algorithm 2 at the context's LDS budget, stopped where images would
-            # replicate the CST beyond 16 times its size; CSTs above 64 MB are not
-            # tried (at a 40 KB budget they need thousands of images at best)
-            if infos[i]["bytes"] > (64 << 20):
-                parts[i] = "skipped"
+            # Algorithm 2 at the context's LDS budget on the first few CSTs only:
+            # on this graph every one tried so far replicated beyond 16 times its
+            # size, and finding that out takes seconds to minutes per CST
+            if i >= n_partition:
                 continue
             t = time.time()
             try:
