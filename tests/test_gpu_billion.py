@@ -5,10 +5,11 @@ min(#embeddings, 10^6).
 One session generates the graph (native generator), builds every CST, tries
 Algorithm 2 at the LDS budget on the first few (reporting the partition count,
 or that the images would replicate the CST beyond 16 times its size), counts
-the queries in persistent launches over groups that fit a device-memory share,
-and checks the counts against the oracle on the host for the queries it
-finishes within its per-query time limit (fastest GPU queries first, as long
-as the session's oracle time lasts).
+each query in its own launch under a deadline (INF when it does not finish),
+counts the finished ones again in persistent launches over groups that fit a
+device-memory share, and checks the counts against the oracle on the host for
+the queries it finishes within its per-query time limit (fastest GPU queries
+first, as long as the session's oracle time lasts).
 
 Generating the graph takes minutes and about 30 GB of host memory, so the test
 runs only when CSTM_BILLION=1 is set.
@@ -60,62 +61,69 @@ def test_billion_edge_batch_with_oracle_parity():
                    torch.from_numpy(g.label).cuda())
     torch.cuda.synchronize()
     say("graph resident on the device")
-    # groups of queries whose CST bounds fit a device-memory share; each group is
-    # built, partitioned (reported), counted in one persistent launch and freed
-    share = 96 << 30
+    # one query per launch first, each under a deadline (the paper's INF rule:
+    # a query that does not finish in time is reported, not counted)
+    limit_s = float(os.environ.get("CSTM_BILLION_DEADLINE_S", "10"))
     est = [G.estimate_bytes(q.qlabel, q.qedges) for q in qs]
-    groups, cur, cur_b = [], [], 0
-    for i, e in enumerate(est):
-        if cur and cur_b + e > share:
-            groups.append(cur)
-            cur, cur_b = [], 0
-        cur.append(i)
-        cur_b += e
-    groups.append(cur)
-    say(f"{len(groups)} launch groups; largest CST bound {max(est)} bytes")
-    counts = [0] * len(qs)
-    gpu_ms = [0.0] * len(qs)
+    counts = [None] * len(qs)
+    gpu_ms = [None] * len(qs)
     infos = [None] * len(qs)
     parts = [None] * len(qs)
-    build_s = batch_s = 0.0
     n_partition = int(os.environ.get("CSTM_BILLION_PARTITIONS", "4"))
-    for grp in groups:
-        csts = []
-        for i in grp:
-            t = time.time()
-            csts.append(cstm.CST(ctx, G, qs[i].qlabel, qs[i].qedges))
-            build_s += time.time() - t
-            infos[i] = csts[-1].info()
-            say(f"query {i} k={qs[i].k}: CST {infos[i]['bytes']} bytes built in {time.time() - t:.2f}s")
-        for i, c in zip(grp, csts):
-            # Algorithm 2 at the context's LDS budget on the first few CSTs only:
-            # on this graph every one tried so far replicated beyond 16 times its
-            # size, and finding that out takes seconds to minutes per CST
-            if i >= n_partition:
-                continue
-            t = time.time()
+    build_s = 0.0
+    for i, q in enumerate(qs):
+        t = time.time()
+        c = cstm.CST(ctx, G, q.qlabel, q.qedges)
+        build_s += time.time() - t
+        infos[i] = c.info()
+        if i < n_partition:
+            # Algorithm 2 at the context's LDS budget, stopped where the images
+            # would replicate the CST beyond 16 times its size
+            tp = time.time()
             try:
                 parts[i] = c.partition(0, 0, 16 * max(infos[i]["bytes"], 4096))
             except cstm.CstmError:
                 parts[i] = "over 16x"
-            say(f"query {i}: partition {parts[i]} in {time.time() - t:.2f}s")
-        cstm.batch_count(ctx, csts, limits=[limit] * len(csts))
+            say(f"query {i}: partition {parts[i]} in {time.time() - tp:.2f}s")
+        t = time.perf_counter()
+        try:
+            counts[i] = c.count(limit=limit, deadline_s=limit_s)
+            gpu_ms[i] = 1e3 * (time.perf_counter() - t)
+        except cstm.CstmError as e:
+            assert e.status == cstm.ETIMEOUT
+        c.close()
+        say(f"query {i} k={q.k}: CST {infos[i]['bytes']} B, count {counts[i]}, "
+            f"{'%.1f ms' % gpu_ms[i] if gpu_ms[i] is not None else 'INF'}")
+    done = [i for i in range(len(qs)) if counts[i] is not None]
+    say(f"{len(done)} of {len(qs)} finished within {limit_s:.0f}s on the GPU; builds {build_s:.1f}s")
+
+    # the finished queries again, in persistent launches over groups that fit a
+    # device-memory share; every count must equal the one-query launch
+    share = 96 << 30
+    groups, cur, cur_b = [], [], 0
+    for i in done:
+        if cur and cur_b + est[i] > share:
+            groups.append(cur)
+            cur, cur_b = [], 0
+        cur.append(i)
+        cur_b += est[i]
+    if cur:
+        groups.append(cur)
+    batch_s = 0.0
+    for grp in groups:
+        csts = [cstm.CST(ctx, G, qs[i].qlabel, qs[i].qedges) for i in grp]
         t = time.perf_counter()
         got = cstm.batch_count(ctx, csts, limits=[limit] * len(csts))
-        batch_s += time.perf_counter() - t
-        for i, c, n in zip(grp, csts, got):
-            counts[i] = n
-            t = time.perf_counter()
-            assert c.count(limit=limit) == n  # one query per launch agrees with the batch
-            gpu_ms[i] = 1e3 * (time.perf_counter() - t)
+        dt = time.perf_counter() - t
+        batch_s += dt
+        for c in csts:
             c.close()
-        say(f"group of {len(grp)}: batched launch {1e3 * (time.perf_counter() - t):.1f} ms incl. per-query checks")
+        assert got == [counts[i] for i in grp]
+        say(f"batched launch of {len(grp)} queries: {dt * 1e3:.1f} ms")
     n_ok = sum(isinstance(p, int) for p in parts)
-    say(f"built in {build_s:.1f}s; partitioned {n_ok} of {len(qs)} within the replication cap; "
-        f"batched launches {batch_s * 1e3:.1f} ms, {sum(counts)} embeddings")
 
     # oracle parity, fastest GPU queries first, within the session's oracle time
-    order = sorted(range(len(qs)), key=lambda i: gpu_ms[i])
+    order = sorted(done, key=lambda i: gpu_ms[i])
     checked, inf, oracle_s = 0, 0, 0.0
     for i in order:
         if oracle_s > 240.0:
@@ -132,10 +140,11 @@ def test_billion_edge_batch_with_oracle_parity():
         checked += 1
     summary = {
         "graph": {"n": g.n, "m": g.m, "max_degree": int(np.diff(g.row_ptr).max())},
-        "queries": len(qs), "limit": limit, "build_s": build_s, "launch_groups": len(groups),
-        "partitioned_within_cap": n_ok, "parts": parts,
+        "queries": len(qs), "limit": limit, "build_s": build_s, "gpu_deadline_s": limit_s,
+        "finished_on_gpu": len(done), "launch_groups": len(groups),
+        "partitioned_within_cap": n_ok, "parts": parts[:n_partition],
         "cst_bytes": [i["bytes"] for i in infos], "cst_bound_bytes": est,
-        "batched_ms": batch_s * 1e3, "embeddings": sum(counts),
+        "batched_ms": batch_s * 1e3, "embeddings": sum(counts[i] for i in done),
         "per_query_gpu_ms": gpu_ms,
         "oracle": {"checked": checked, "inf": inf, "seconds": oracle_s, "threads": oracle.num_cores()},
     }
