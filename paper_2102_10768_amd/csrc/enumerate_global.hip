@@ -70,6 +70,7 @@ struct GArgs {
     int last_sum;               // > 0: count an unconstrained last level by list lengths
     const unsigned long long* limits;  // per query: stop once its count reaches this (0: none); nullptr: none
     unsigned int* qstop;               // per query: set once its limit was reached
+    bool small_lists;                  // every list shorter than 2^23: 128 lengths sum in 32 bits
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
@@ -104,6 +105,25 @@ __device__ inline T ld_rlx(T* p) {
 }
 
 __device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (VALU only, no LDS permutes); every lane must be active.
+__device__ inline int32_t wave_incl_add(int32_t x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+// Sum over the 64 lanes; 32-bit when the caller knows it cannot overflow.
+__device__ inline int64_t wave_sum(int64_t x, bool small) {
+    if (small) return (int64_t)__builtin_amdgcn_readlane(wave_incl_add((int32_t)x), CSTM_WAVE - 1);
+    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, CSTM_WAVE);
+    return x;
+}
 
 // Binary search of x in the ascending array a[lo, hi).
 __device__ inline bool contains(const int32_t* a, int64_t lo, int64_t hi, int32_t x) {
@@ -207,8 +227,7 @@ __device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, boo
         const int32_t x = pk == d ? v : rl(pl, pk);
         len = toffL[x + 1] - toffL[x];
     }
-    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) len += __shfl_xor(len, o, CSTM_WAVE);
-    return len;
+    return wave_sum(len, A.small_lists);
 }
 
 // Expand level L = d + 1 for every survivor (lanes with ok) of the current
@@ -241,12 +260,8 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
         b0 = toffL[x];
         len = (int32_t)(toffL[x + 1] - b0);
     }
-    int32_t incl = len;  // inclusive prefix over lanes
-    for (int o = 1; o < CSTM_WAVE; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o, CSTM_WAVE);
-        if (lane >= o) incl += y;
-    }
-    const int32_t total = __shfl(incl, CSTM_WAVE - 1);
+    const int32_t incl = wave_incl_add(len);  // inclusive prefix over lanes
+    const int32_t total = __builtin_amdgcn_readlane(incl, CSTM_WAVE - 1);
     uint64_t passed = 0;
     // Two rounds of 64 pairs per iteration: their owner searches and loads are
     // independent, so each hides the other's latency.
@@ -311,7 +326,7 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
                     lk += toffK[xk + 1] - toffK[xk];
                 }
             }
-            for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) lk += __shfl_xor(lk, o, CSTM_WAVE);
+            lk = wave_sum(lk, A.small_lists);
             cnt += (uint64_t)lk;
             nN += (uint64_t)lk;
             nS += (uint64_t)lk;
@@ -709,6 +724,9 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.stats = ctx->tune.collect_stats ? work : nullptr;
     A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
     A.deadline = o.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)o.deadline_ms : 0;
+    int64_t longest = 0;
+    for (int q = 0; q < nq; ++q) longest = std::max<int64_t>(longest, csts[q]->d_cst);
+    A.small_lists = longest < (int64_t(1) << 23);
     A.limits = any_limit ? dlim : nullptr;
     A.qstop = any_limit ? dstop : nullptr;
     A.donate_period = ctx->tune.hbm_donate_period;
