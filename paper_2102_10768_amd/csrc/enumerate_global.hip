@@ -118,6 +118,17 @@ __device__ inline int32_t wave_incl_add(int32_t x) {
     return x;
 }
 
+// Inclusive prefix maximum over the 64 lanes (values >= -1), the same DPP pattern.
+__device__ inline int32_t wave_incl_max(int32_t x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // Sum over the 64 lanes; 32-bit when the caller knows it cannot overflow.
 __device__ inline int64_t wave_sum(int64_t x, bool small) {
     if (small) return (int64_t)__builtin_amdgcn_readlane(wave_incl_add((int32_t)x), CSTM_WAVE - 1);
@@ -266,29 +277,33 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
     // Two rounds of 64 pairs per iteration: their owner searches and loads are
     // independent, so each hides the other's latency.
     constexpr int R = 2;
+    // Owner lane of each pair: every survivor with a non-empty list marks the
+    // round position where its list starts (starts are distinct), and a prefix
+    // maximum carries each mark forward to the positions its list covers.
+    __shared__ int32_t s_mark[256 / CSTM_WAVE][CSTM_WAVE];
+    int32_t* mark = s_mark[threadIdx.x / CSTM_WAVE];
+    const int32_t start_me = incl - len;
+    int32_t carry = 0;  // owner of the pair just before the current round
     for (int32_t t0 = 0; t0 < total; t0 += R * CSTM_WAVE) {
-        int32_t t[R], lo2[R], hi2[R];
+        int32_t t[R], own[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            t[r] = t0 + r * CSTM_WAVE + lane;
-            lo2[r] = 0;
-            hi2[r] = CSTM_WAVE - 1;
-        }
-        // owner lane of pair t: first lane whose inclusive prefix exceeds t
-#pragma unroll
-        for (int it = 0; it < 6; ++it) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int mid = (lo2[r] + hi2[r]) >> 1;
-                if (__shfl(incl, mid) > t[r]) hi2[r] = mid;
-                else lo2[r] = mid + 1;
-            }
+            const int32_t base = t0 + r * CSTM_WAVE;
+            t[r] = base + lane;
+            mark[lane] = -1;
+            __builtin_amdgcn_wave_barrier();
+            if (len > 0 && start_me >= base && start_me < base + CSTM_WAVE) mark[start_me - base] = lane;
+            __builtin_amdgcn_wave_barrier();
+            const int32_t m = wave_incl_max(mark[lane]);
+            __builtin_amdgcn_wave_barrier();
+            own[r] = m > carry ? m : carry;
+            carry = __builtin_amdgcn_readlane(own[r], CSTM_WAVE - 1);
         }
         bool val2[R], ok2[R];
         int32_t v2[R], g2[R], vs[R], gs[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int sl = lo2[r];
+            const int sl = own[r];
             val2[r] = t[r] < total;
             const int32_t start = __shfl(incl, sl) - __shfl(len, sl);
             const int64_t bs = __shfl(b0, sl);
