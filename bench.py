@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the default launch parameters")
+    ap.add_argument("--served-requests", type=int, default=120,
+                    help="requests in the short served-vs-plain comparison of the default run (0: skip)")
+    ap.add_argument("--served-qps", type=float, default=25.0, help="arrival rate of that comparison")
     ap.add_argument("--serve", action="store_true",
                     help="request-serving form: Poisson arrivals, served loop vs one-at-a-time, p50/p99 latency")
     ap.add_argument("--rates", default="", help="arrival rates (queries/s) for --serve (default: the workload's)")
@@ -256,6 +259,19 @@ def main():
             "avg_launch_ms": kern_ms / max(1, launches),
         },
     }
+    # served form on the same pool: a short Poisson stream through the library's
+    # server and through the one-at-a-time form (p50/p99 latency, throughput)
+    if a.served_requests > 0:
+        ctx.tune = {"hbm_wgs_per_cu": 0, "hbm_donate_min": 0, "hbm_donate_period": 0, "hbm_flat_max": 0,
+                    "hbm_donate_last_min": 0, "enum_mode": mode_id}
+        row, bad_s = served_vs_plain(ctx, G, queries, expected, a.served_requests, a.served_qps, 201)
+        out["served"] = {"form": "cstm_server (2 builders, 2 lanes, batching window 2 ms) vs one at a time, "
+                                 "same Poisson arrivals", **row}
+        out["parity"]["checked"] += 2 * a.served_requests
+        out["parity"]["mismatches"] += bad_s
+        bad = bad + ["served"] * bad_s
+        print(f"served: p50 {row['served']['p50_ms']:.1f} ms vs plain {row['plain']['p50_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         import oracle
 
@@ -275,6 +291,31 @@ def main():
     if bad or bad_b:
         print(f"COUNT MISMATCH plain {bad} batched {bad_b}", file=sys.stderr)
         sys.exit(1)
+
+
+def served_vs_plain(ctx, G, queries, expected, n, qps, seed, limit=0, budget=64 << 30, lanes=2, builders=2,
+                    batch_wait_us=2000):
+    """One Poisson request stream through the library's server and through the
+    one-at-a-time form; returns (summary dict, number of wrong counts)."""
+    import numpy as np
+
+    from paper_2102_10768_amd import cstm, serve
+
+    arr = serve.poisson_arrivals(n, qps, seed)
+    picks = np.random.Generator(np.random.PCG64(seed + 100)).integers(0, len(queries), size=n)
+    qs = [queries[int(p)] for p in picks]
+    want = [expected[int(p)] for p in picks]
+    with cstm.Server(ctx, G, mem_budget=budget, lanes=lanes, builders=builders, batch_wait_us=batch_wait_us) as srv:
+        served = serve.replay_native(srv, arr, qs, limit=limit)
+        sst = srv.stats()
+    s_srv = serve.summarize(served)
+    s_srv.update(peak_charged_bytes=sst["peak_bytes"], lane_overlap=sst["max_overlap"], launches=sst["launches"])
+    plain = serve.run_sequential(serve.CstmBackend(ctx, G), arr, qs, limit=limit)
+    s_pl = serve.summarize(plain)
+    bad = sum(r.count != w for r, w in zip(served, want)) + sum(r.count != w for r, w in zip(plain, want))
+    row = {"qps": qps, "requests": n, "served": s_srv, "plain": s_pl,
+           "served_vs_plain": (s_srv["embeddings_per_s"] / s_pl["embeddings_per_s"]) if s_pl["embeddings_per_s"] else None}
+    return row, bad
 
 
 def serve_main(a, W, g, queries, expected):
