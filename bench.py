@@ -81,7 +81,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
-              f"in DESIGN.md and is not built.", file=sys.stderr)
+              f"in the design notes and is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
