@@ -337,3 +337,10 @@ def _pins_pass(mutate: int) -> bool:
 def test_planted_mistakes_are_caught(mutate):
     assert _pins_pass(0)
     assert not _pins_pass(mutate)
+
+
+def test_maximum_query_size():
+    assert oracle.count(cf.cycle(40), cf.path_query(32)) == cf.path_in_cycle(40, 32)
+    assert oracle.count(cf.path(40), cf.path_query(32)) == cf.path_in_path(40, 32)
+    with pytest.raises(ValueError):
+        oracle.match(cf.cycle(40), cf.path_query(33))
