@@ -106,7 +106,10 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      level up adds the length of that list to the count
  *                      instead of visiting it (reported in
  *                      cstm_enum_stats.summed).  1 (default): on; negative:
- *                      off.  Listing always visits every candidate.          */
+ *                      off.  Listing always visits every candidate.
+ *   batch_order        HBM mode, several CSTs in one launch: 0 (default)
+ *                      seeds the heaviest first by W_CST (cstm_cst_workload);
+ *                      negative: in the order given.                         */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -125,6 +128,7 @@ typedef struct {
     int32_t hbm_donate_last_min;
     int32_t last_level_sum;
     int32_t hbm_donate_min;
+    int32_t batch_order;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).
@@ -203,6 +207,17 @@ cstm_status cstm_graph_info(const cstm_graph* g, int64_t* n, int64_t* nnz, int32
 cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
                            int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out);
 
+/* As cstm_cst_build, with the caller's matching order (host, k entries: a
+ * permutation of the query vertices that starts at the CST root and places
+ * every vertex after its BFS-tree parent) instead of the path-based order of
+ * Section V-B; NULL = the path-based order.  The order changes only the work
+ * (Section VII-C studies its effect), never the embeddings.  CSTM_EINVAL for
+ * an order that breaks these rules (the root is the vertex minimising
+ * #C0(u)/d_q(u), see cstm_cst_info_get). */
+cstm_status cstm_cst_build_ordered(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
+                                   int32_t m_q, const int32_t* qedges, const int32_t* order, void* stream,
+                                   cstm_cst** out);
+
 /* Upper bound on the device bytes cstm_cst_build requests for the query
  * (k, qlabel, m_q, qedges as for cstm_cst_build): the CST of Section IV-A plus
  * its build-time tables, from the label index alone.  #C(u) is at most the
@@ -225,6 +240,15 @@ cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const int32_t* qla
  * *n_parts_out (may be NULL) receives the number of partitions. */
 cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max_list_len,
                                uint64_t max_total_bytes, int64_t* n_parts_out);
+
+/* Workload estimate W_CST of Section V-C: with c_u(v) = product over u's tree
+ * children u' of the sum of c_u'(v') over v's candidate list in C(u') (1 at
+ * the leaves), W_CST = sum of c_root over the root's candidates.  It counts
+ * the tree-shaped paths the CST holds: an upper bound on the embeddings, equal
+ * to their number for tree queries with pairwise-distinct labels.  Computed on
+ * the device in double precision (exact below 2^53) and cached in the CST;
+ * batched launches use it to start the heaviest queries first. */
+cstm_status cstm_cst_workload(cstm_cst* cst, double* w_out);
 
 cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
 

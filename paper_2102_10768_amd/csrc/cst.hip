@@ -297,6 +297,23 @@ __global__ void k_sum_sat(const uint64_t* __restrict__ v, int64_t n, unsigned lo
     }
 }
 
+// Workload DP (Section V-C) for one tree edge (u_p -> u): the value of each
+// candidate of u_p is multiplied by the sum of the values of its list in C(u).
+__global__ void k_workload_step(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int64_t np,
+                                const double* __restrict__ cu, double* __restrict__ cp) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+        double sum = 0.0;
+        for (int64_t j = off[i]; j < off[i + 1]; ++j) sum += cu[adj[j]];
+        cp[i] *= sum;
+    }
+}
+
+__global__ void k_fill_ones(double* __restrict__ x, int64_t n) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 1.0;
+}
+
 constexpr int kWaveBlock = 256;
 
 unsigned wave_grid(int64_t items) {
@@ -308,6 +325,7 @@ struct QueryPrep {
     int k;
     int32_t qlabel[CSTM_MAX_K];
     uint32_t adj[CSTM_MAX_K];
+    const int32_t* order = nullptr;  // caller's matching order, or nullptr for the path-based one
 };
 
 void validate_query(int32_t k, const int32_t* qlabel, int32_t m_q, const int32_t* qedges, QueryPrep& q) {
@@ -551,8 +569,20 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             c->d_cst = std::max(c->d_cst, c->tree[u].max_len);
         }
     }
-    // 4b. path-based matching order
-    {
+    // 4b. matching order: the caller's (checked against the tree) or the path-based one
+    if (q.order) {
+        uint32_t placed = 0;
+        for (int i = 0; i < k; ++i) {
+            const int u = q.order[i];
+            CSTM_REQUIRE(u >= 0 && u < k && !(placed >> u & 1u), CSTM_EINVAL, "order is not a permutation of 0..k-1");
+            CSTM_REQUIRE(i > 0 || u == root, CSTM_EINVAL, "order must start at the CST root");
+            CSTM_REQUIRE(i == 0 || (placed >> c->parent[u] & 1u), CSTM_EINVAL,
+                         "order must place every vertex after its tree parent");
+            placed |= 1u << u;
+            c->order[i] = u;
+        }
+        for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
+    } else {
         std::vector<std::pair<std::pair<uint64_t, int>, std::vector<int>>> paths;
         for (int leaf = 0; leaf < k; ++leaf) {
             bool has_child = false;
@@ -671,14 +701,16 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     HIP_TRY(hipStreamSynchronize(s));
 }
 
-extern "C" cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
-                                      int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out) {
+extern "C" cstm_status cstm_cst_build_ordered(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
+                                              int32_t m_q, const int32_t* qedges, const int32_t* order, void* stream,
+                                              cstm_cst** out) {
     cstm_cst* c = nullptr;
     cstm_status st = cstm_guard([&] {
         CSTM_REQUIRE(ctx && g && out, CSTM_EINVAL, "NULL argument");
         *out = nullptr;
         QueryPrep q;
         validate_query(k, qlabel, m_q, qedges, q);
+        q.order = order;
         HIP_TRY(hipSetDevice(ctx->device));
         c = new cstm_cst();
         c->ctx = ctx;
@@ -690,8 +722,18 @@ extern "C" cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_
         c->t_build = tm.stop();
         *out = c;
     });
-    if (st != CSTM_OK && c) delete c;
+    if (st != CSTM_OK && c) {
+        // kernels of a half-built tree may still run on the stream: let them
+        // finish before their blocks go back to the pool
+        (void)hipStreamSynchronize(c->stream);
+        delete c;
+    }
     return st;
+}
+
+extern "C" cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
+                                      int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out) {
+    return cstm_cst_build_ordered(ctx, g, k, qlabel, m_q, qedges, nullptr, stream, out);
 }
 
 extern "C" void cstm_cst_free(cstm_cst* cst) {
@@ -733,6 +775,50 @@ extern "C" cstm_status cstm_cst_candidates(const cstm_cst* c, int32_t u, int32_t
             HIP_TRY(hipMemcpyAsync(out, c->cand[u], w * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
         }
+    });
+}
+
+// W_CST = sum over root candidates of c_root, where c_u(v) is the product over
+// u's tree children u' of the sum of c_u'(v') over v's list in C(u') (1 at the
+// leaves): the number of tree-shaped paths the CST holds, an upper bound on
+// the embeddings below each candidate (Section V-C).  In double precision,
+// exact while the values stay below 2^53.
+double cstm_cst_workload_run(cstm_cst* c) {
+    if (c->workload >= 0) return c->workload;
+    if (c->empty) return c->workload = 0.0;
+    hipStream_t s = c->stream;
+    DevArena mem;
+    mem.ctx = c->ctx;
+    double* val[CSTM_MAX_K] = {};
+    for (int u = 0; u < c->k; ++u) {
+        const int64_t n = c->ncand[u];
+        val[u] = mem.get_n<double>(n ? n : 1);
+        if (n) {
+            k_fill_ones<<<cstm_blocks(n, 256, 4096), 256, 0, s>>>(val[u], n);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    for (int t = c->k - 1; t >= 1; --t) {
+        const int u = c->bfs[t], p = c->parent[u];
+        const int64_t np = c->ncand[p];
+        if (!np) continue;
+        k_workload_step<<<cstm_blocks(np, 256, 4096), 256, 0, s>>>(c->tree[u].off, c->tree[u].adj, np, val[u], val[p]);
+        HIP_TRY(hipGetLastError());
+    }
+    const int64_t nr = c->ncand[c->root];
+    std::vector<double> h((size_t)nr);
+    if (nr) HIP_TRY(hipMemcpyAsync(h.data(), val[c->root], (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double w = 0.0;
+    for (double x : h) w += x;  // in candidate order: the same result every time
+    return c->workload = w;
+}
+
+extern "C" cstm_status cstm_cst_workload(cstm_cst* c, double* w_out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(c && w_out, CSTM_EINVAL, "NULL argument");
+        HIP_TRY(hipSetDevice(c->ctx->device));
+        *w_out = cstm_cst_workload_run(c);
     });
 }
 

@@ -632,17 +632,24 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
 
 // Initial tasks: runs of root candidates of every query.
 __global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t* __restrict__ nroot,
-                       const int64_t* __restrict__ chunk, int nq, unsigned long long total) {
+                       const int64_t* __restrict__ chunk, const int32_t* __restrict__ perm, int nq,
+                       unsigned long long total) {
     unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     for (unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        int q = 0;
-        while (q + 1 < nq && (long long)t >= first[q + 1]) ++q;
-        const int64_t i = (int64_t)t - first[q];
+        // seeding position i: the last with first[i] <= t
+        int lo = 0, hi = nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((long long)t >= first[mid]) lo = mid;
+            else hi = mid - 1;
+        }
+        const int i = lo;
+        const int64_t r = (int64_t)t - first[i];
         GTask& T = A.tasks[t & A.qmask];
-        T.q = q;
+        T.q = perm[i];
         T.depth = 0;
-        T.lo = i * chunk[q];
-        T.hi = T.lo + chunk[q] < nroot[q] ? T.lo + chunk[q] : nroot[q];
+        T.lo = r * chunk[i];
+        T.hi = T.lo + chunk[i] < nroot[i] ? T.lo + chunk[i] : nroot[i];
         for (int p = 0; p < CSTM_MAX_K; ++p) T.prefix[p] = 0;
         A.ready[t & A.qmask] = (unsigned int)((t >> A.qlog) + 1);
     }
@@ -657,14 +664,24 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
                                const EnumOpts& o, cstm_enum_stats* st, hipStream_t s) {
     const int qlog = 20;
     const unsigned long long qcap = 1ull << qlog;
+    // seeding order: the heaviest queries (largest W_CST, Section V-C) first, so
+    // the long searches start early and the short ones fill in behind them
+    std::vector<int32_t> perm(nq);
+    for (int q = 0; q < nq; ++q) perm[q] = q;
+    if (nq > 1 && ctx->tune.batch_order >= 0) {
+        std::vector<double> w(nq);
+        for (int q = 0; q < nq; ++q) w[q] = cstm_cst_workload_run(csts[q]);
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
+    }
+    // per seeding position: the first task, root candidates and roots per task
     std::vector<int64_t> first(nq + 1, 0), nroot(nq, 0), chunk(nq, 1);
-    for (int q = 0; q < nq; ++q) {
-        const cstm_cst* c = csts[q];
-        nroot[q] = c->empty ? 0 : c->host_desc.pos[0].n;
+    for (int i = 0; i < nq; ++i) {
+        const cstm_cst* c = csts[perm[i]];
+        nroot[i] = c->empty ? 0 : c->host_desc.pos[0].n;
         // one root candidate per task unless the batch would fill half the ring
-        int64_t per = std::max<int64_t>(1, (nroot[q] * 2 * std::max(1, nq) + (int64_t)qcap - 1) / (int64_t)qcap);
-        chunk[q] = per;
-        first[q + 1] = first[q] + (nroot[q] + per - 1) / per;
+        int64_t per = std::max<int64_t>(1, (nroot[i] * 2 * std::max(1, nq) + (int64_t)qcap - 1) / (int64_t)qcap);
+        chunk[i] = per;
+        first[i + 1] = first[i] + (nroot[i] + per - 1) / per;
     }
     const unsigned long long total = (unsigned long long)first[nq];
     CSTM_REQUIRE(total < qcap / 2, CSTM_EINVAL, "too many root candidates for the task ring");
@@ -678,7 +695,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const size_t off_desc = up(off_work + 8 * sizeof(unsigned long long));
     const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
     const size_t off_slot = up(off_meta + (3 * (size_t)nq + 1) * sizeof(int64_t));
-    const size_t off_lim = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t off_perm = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t off_lim = up(off_perm + (size_t)nq * sizeof(int32_t));
     const size_t off_stop = up(off_lim + (size_t)nq * sizeof(unsigned long long));
     const size_t need = up(off_stop + (size_t)nq * sizeof(unsigned int));
     const size_t ready_b = qcap * sizeof(unsigned int);
@@ -695,6 +713,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     CstDev* descs = (CstDev*)(ws + off_desc);
     int64_t* meta = (int64_t*)(ws + off_meta);
     int32_t* dslot = (int32_t*)(ws + off_slot);
+    int32_t* dperm = (int32_t*)(ws + off_perm);
     unsigned long long* dlim = (unsigned long long*)(ws + off_lim);
     unsigned int* dstop = (unsigned int*)(ws + off_stop);
     bool any_limit = false;
@@ -721,6 +740,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     HIP_TRY(hipMemcpyAsync(meta + nq + 1, nroot.data(), nq * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(meta + 2 * nq + 1, chunk.data(), nq * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(dslot, slot, nq * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dperm, perm.data(), nq * 4, hipMemcpyHostToDevice, s));
     GArgs A;
     A.descs = descs;
     A.slot = dslot;
@@ -749,8 +769,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
     A.donate_last_min = ctx->tune.hbm_donate_last_min;
     A.last_sum = ctx->tune.last_level_sum;
-    k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, nq,
-                                                                  total);
+    k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, dperm,
+                                                                  nq, total);
     HIP_TRY(hipGetLastError());
     hipEvent_t ev[2];
     HIP_TRY(hipEventCreate(&ev[0]));

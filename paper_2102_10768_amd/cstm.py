@@ -44,6 +44,7 @@ class cstm_tune(ctypes.Structure):
         ("hbm_donate_last_min", ctypes.c_int32),
         ("last_level_sum", ctypes.c_int32),
         ("hbm_donate_min", ctypes.c_int32),
+        ("batch_order", ctypes.c_int32),
     ]
 
 
@@ -122,7 +123,7 @@ EXPORTS = [
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
     "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
     "cstm_server_create", "cstm_server_submit", "cstm_server_poll", "cstm_server_wait", "cstm_server_get_stats",
-    "cstm_server_destroy",
+    "cstm_server_destroy", "cstm_cst_workload", "cstm_cst_build_ordered",
 ]
 
 _lib = None
@@ -171,6 +172,8 @@ def load_library():
         "cstm_server_wait": (st, [P, U64, ctypes.c_double, ctypes.POINTER(cstm_request_result)]),
         "cstm_server_get_stats": (st, [P, ctypes.POINTER(cstm_server_stats)]),
         "cstm_server_destroy": (None, [P]),
+        "cstm_cst_workload": (st, [P, ctypes.POINTER(ctypes.c_double)]),
+        "cstm_cst_build_ordered": (st, [P, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -334,15 +337,27 @@ class Graph:
 class CST:
     """One query's candidate search tree (``cstm_cst_build``)."""
 
-    def __init__(self, ctx: Context, graph: Graph, qlabel, qedges, stream=None):
+    def __init__(self, ctx: Context, graph: Graph, qlabel, qedges, stream=None, order=None):
+        """``order``: the matching order (a permutation of the query vertices
+        that starts at the CST root and puts every vertex after its BFS-tree
+        parent); None keeps the path-based order of Section V-B."""
         lib = load_library()
         self.ctx, self.graph = ctx, graph
         ql = np.ascontiguousarray(qlabel, dtype=np.int32)
         qe = np.ascontiguousarray(np.asarray(qedges, dtype=np.int32).reshape(-1, 2))
         self.k = int(ql.shape[0])
         h = ctypes.c_void_p()
-        _check(lib.cstm_cst_build(ctx.handle, graph.handle, self.k, ql.ctypes.data, int(qe.shape[0]),
-                                  qe.ctypes.data if qe.size else None, _stream_ptr(stream), ctypes.byref(h)))
+        if order is None:
+            _check(lib.cstm_cst_build(ctx.handle, graph.handle, self.k, ql.ctypes.data, int(qe.shape[0]),
+                                      qe.ctypes.data if qe.size else None, _stream_ptr(stream),
+                                      ctypes.byref(h)))
+        else:
+            od = np.ascontiguousarray(order, dtype=np.int32)
+            if od.shape != (self.k,):
+                raise ValueError(f"order must hold {self.k} vertices, got shape {od.shape}")
+            _check(lib.cstm_cst_build_ordered(ctx.handle, graph.handle, self.k, ql.ctypes.data,
+                                              int(qe.shape[0]), qe.ctypes.data if qe.size else None,
+                                              od.ctypes.data, _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
         ctx._children.add(self)
 
@@ -353,6 +368,12 @@ class CST:
         _check(load_library().cstm_cst_partition(self.handle, int(budget_bytes), int(max_list_len),
                                                  int(max_total_bytes), ctypes.byref(n)))
         return n.value
+
+    def workload(self) -> float:
+        """W_CST of the workload DP (Section V-C)."""
+        w = ctypes.c_double()
+        _check(load_library().cstm_cst_workload(self.handle, ctypes.byref(w)))
+        return w.value
 
     def info(self) -> dict:
         i = cstm_cst_info()

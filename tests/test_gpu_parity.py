@@ -211,3 +211,120 @@ def test_malformed_inputs_rejected():
         cstm.CST(ctx(), G, [0, 0, 0], [(0, 1)])  # disconnected
     with pytest.raises(cstm.CstmError):
         cstm.CST(ctx(), G, [0, 0], [(0, 0)])  # self-loop
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_maximum_query_size_and_edgeless_graphs(mode):
+    """k = 32 (the largest query): P_32 has 2n embeddings in C_n and 2(n-31)
+    in P_n; on a graph without edges only single-vertex queries match."""
+    from paper_2102_10768_amd import cstm
+
+    G = gpu_graph(cf.cycle(40), mode)
+    assert gpu_count(G, cf.path_query(32), partition=mode == "lds")[0] == cf.path_in_cycle(40, 32)
+    G = gpu_graph(cf.path(40), mode)
+    assert gpu_count(G, cf.path_query(32), partition=mode == "lds")[0] == cf.path_in_path(40, 32)
+    with pytest.raises(cstm.CstmError):
+        gpu_count(G, cf.path_query(33))
+    empty = cf.graph_from_edges(50, [], np.arange(50) % 3)
+    G = gpu_graph(empty, mode)
+    assert gpu_count(G, cf.query([1], []))[0] == int((empty.label == 1).sum())
+    assert gpu_count(G, cf.query([0, 0], [(0, 1)]))[0] == 0
+
+
+def test_workload_estimate_matches_reference_dp():
+    """W_CST on the device (Section V-C) equals the reference DP exactly, and
+    the number of embeddings for a tree query with pairwise-distinct labels."""
+    g = _c1()
+    G = gpu_graph(g)
+    from paper_2102_10768_amd import cstm
+
+    for q in query_set(g, [3, 4, 5, 6, 7] * 3, 57):
+        ref = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        _, w_ref = cst_ref.workload(ref)
+        c = cstm.CST(ctx(), G, q.qlabel, q.qedges)
+        w = c.workload()
+        assert w == float(w_ref)
+        n = c.count()
+        c.close()
+        assert w >= n
+        if cf.is_tree_with_distinct_labels(q):
+            assert w == n
+    # the worked example of Section V-C on the fixture graph
+    fx = json.load(open(os.path.join(GOLDEN, "fig4_fixture.json")))
+    gf = cf.graph_from_edges(fx["n"], [tuple(e) for e in fx["edges"]], fx["labels"])
+    qf = cf.query(fx["query"]["qlabel"], [tuple(e) for e in fx["query"]["qedges"]])
+    ref = cst_ref.build_cst(gf, qf.qlabel, qf.qedges)
+    c = cstm.CST(ctx(), gpu_graph(gf), qf.qlabel, qf.qedges)
+    assert c.workload() == float(cst_ref.workload(ref)[1])
+    c.close()
+
+
+def test_batch_seeding_order_does_not_change_counts():
+    g = _c1()
+    G = gpu_graph(g, "hbm")
+    from paper_2102_10768_amd import cstm
+
+    qs = query_set(g, [3, 4, 5, 6] * 4, 73)
+    csts = [cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges) for q in qs]
+    by_w = cstm.batch_count(ctx("hbm"), csts)
+    ctx("hbm").tune = {"batch_order": -1}
+    try:
+        given = cstm.batch_count(ctx("hbm"), csts)
+    finally:
+        ctx("hbm").tune = {"batch_order": 0}
+    alone = [c.count() for c in csts]
+    for c in csts:
+        c.close()
+    assert by_w == given == alone
+
+
+def _sorted_rows(c):
+    n, rows = c.list(1 << 16)
+    return n, sorted(tuple(int(x) for x in row) for row in rows.cpu().numpy())
+
+
+def _tree_orders(parent, root, rng, n):
+    """n random orders that start at the root and put every vertex after its
+    tree parent (the orders Section VII-C varies)."""
+    k = len(parent)
+    out = []
+    for _ in range(n):
+        order, placed = [root], {root}
+        while len(order) < k:
+            ready = [u for u in range(k) if u not in placed and parent[u] in placed]
+            u = int(rng.choice(ready))
+            order.append(u)
+            placed.add(u)
+        out.append(order)
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", MODES)
+def test_caller_matching_order_keeps_embeddings(mode):
+    g = _c1()
+    G = gpu_graph(g, mode)
+    from paper_2102_10768_amd import cstm
+
+    rng = np.random.default_rng(91)
+    for q in query_set(g, [4, 5, 6, 7], 92):
+        base = cstm.CST(ctx(mode), G, q.qlabel, q.qedges)
+        info = base.info()
+        want_n = base.count()
+        want_rows = _sorted_rows(base)
+        base.close()
+        assert want_n == oracle.match(g, q).count
+        for order in _tree_orders(info["parent"], info["root"], rng, 3):
+            c = cstm.CST(ctx(mode), G, q.qlabel, q.qedges, order=order)
+            assert c.info()["order"] == order
+            assert c.count() == want_n
+            assert _sorted_rows(c) == want_rows
+            c.close()
+        # an order that breaks the tree (root not first, or a child before its parent)
+        bad = list(info["order"])
+        bad[0], bad[1] = bad[1], bad[0]
+        with pytest.raises(cstm.CstmError) as e:
+            cstm.CST(ctx(mode), G, q.qlabel, q.qedges, order=bad)
+        assert e.value.status == cstm.EINVAL
+        with pytest.raises(cstm.CstmError):
+            cstm.CST(ctx(mode), G, q.qlabel, q.qedges, order=[info["root"]] * q.k)
