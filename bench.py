@@ -12,6 +12,11 @@ values stored with the workload.  The graph is generated from its seed and
 made resident before timing starts.
 
 Prints one JSON line (see the keys below); exits 1 if a count is wrong.
+
+    python bench.py --workload c2 --share 0,0.01,0.1 [--host-threads 16]
+
+sweeps the host-core share of Algorithm 3 instead (CSTs built beforehand, one
+JSON line per delta, counts checked).
 """
 
 from __future__ import annotations
@@ -78,6 +83,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=2, help="--serve: enumeration lanes (streams)")
     ap.add_argument("--builders", type=int, default=2, help="--serve: CST builder threads (streams)")
     ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
+    ap.add_argument("--share", default="", help="comma-separated deltas: sweep the host-core share (Algorithm 3)")
+    ap.add_argument("--host-threads", type=int, default=0, help="--share: host threads (0: the host's cores, <= 16)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
@@ -102,6 +109,8 @@ def main():
 
     if a.serve:
         return serve_main(a, W, g, queries, expected)
+    if a.share:
+        return share_main(a, W, g, queries, expected)
 
     mode_id = {"auto": 0, "lds": 1, "hbm": 2}[a.mode]
     ctx = cstm.Context(0, tune={"enum_mode": mode_id, "collect_stats": 0})
@@ -317,6 +326,49 @@ def served_vs_plain(ctx, G, queries, expected, n, qps, seed, limit=0, budget=64 
     row = {"qps": qps, "requests": n, "served": s_srv, "plain": s_pl,
            "served_vs_plain": (s_srv["embeddings_per_s"] / s_pl["embeddings_per_s"]) if s_pl["embeddings_per_s"] else None}
     return row, bad
+
+
+def share_main(a, W, g, queries, expected):
+    """Algorithm 3 sweep: the host cores take a share of at most delta of each
+    query's W_CST, the GPU the rest; one JSON line per delta (counts checked)."""
+    import torch
+
+    from paper_2102_10768_amd import cstm
+
+    ctx = cstm.Context(0, tune={"enum_mode": 2, "collect_stats": 0})
+    G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
+                   torch.from_numpy(g.label).cuda())
+    csts = [cstm.CST(ctx, G, q.qlabel, q.qedges) for q in queries]
+    for c in csts:
+        c.workload()
+    total = sum(expected)
+    for delta in [float(x) for x in a.share.split(",")]:
+        for _ in range(max(0, a.warmup)):
+            for c in csts:
+                c.count_shared(delta, host_threads=a.host_threads)
+        keys = ("w_host", "w_device", "count_host", "count_device", "copy_ms", "host_ms", "device_ms", "wall_ms")
+        agg = dict.fromkeys(keys, 0.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            for c, want in zip(csts, expected):
+                n, st = c.count_shared(delta, host_threads=a.host_threads)
+                if n != want:
+                    raise SystemExit(f"count mismatch at delta {delta}: {n} != {want}")
+                for k in keys:
+                    agg[k] += st[k] / a.steps
+        dt = (time.perf_counter() - t) / a.steps
+        print(json.dumps({"workload": a.workload, "delta": delta, "queries": len(csts), "embeddings": total,
+                          "ms_per_step": round(dt * 1e3, 3), "embeddings_per_s": total / dt,
+                          "host_share_of_W": agg["w_host"] / max(agg["w_host"] + agg["w_device"], 1e-300),
+                          "host_share_of_count": agg["count_host"] / max(total, 1),
+                          "host_threads": st["host_threads"],
+                          **{k: round(agg[k], 3) for k in ("copy_ms", "host_ms", "device_ms", "wall_ms")}}),
+              flush=True)
+    for c in csts:
+        c.close()
+    G.close()
+    ctx.close()
 
 
 def serve_main(a, W, g, queries, expected):

@@ -282,6 +282,36 @@ cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* row
 cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, const uint64_t* limits,
                                  uint64_t* counts_out, void* stream);
 
+/* ---------------------------------------------------------------- host share
+ * Algorithm 3 (Section V-C): the root candidates of the CST are cut into
+ * n_runs runs of consecutive candidates (0 = min(1024, #roots)), each weighed
+ * by the sum of c_root(v) over it (the workload DP, see cstm_cst_workload).
+ * In root order, a run goes to the host cores when W_C + W_run <
+ * delta * (W_C + W_F + W_run), else to the GPU (W_C, W_F: the workload handed
+ * to each so far), so the host's share of W_CST stays below delta.  The GPU
+ * counts its runs with the HBM-resident kernel (whatever the context's
+ * enum_mode) while host_threads threads (0 = the host's cores, at most 16)
+ * count the others by backtracking over a host copy of the CST lists; the two
+ * overlap.  *count_out = the total number of embeddings (host + GPU); st (may
+ * be NULL) receives the split and its times.  delta = 0 gives everything to
+ * the GPU.  Counts only (no listing, no limit); the context's deadline_ms
+ * applies to the GPU part.  CSTM_EINVAL for delta outside [0, 1], negative
+ * n_runs or host_threads outside [0, 256]. */
+typedef struct cstm_share_stats {
+    double delta;
+    double w_host, w_device;         /* W_C and W_F after the last run */
+    int64_t groups_host, groups_device;  /* runs each side received */
+    uint64_t count_host, count_device;
+    double copy_ms;                  /* until the host copy of the lists was complete */
+    double host_ms;                  /* until the last host thread ended (0: no host runs) */
+    double device_ms;                /* until the GPU's count was back */
+    double wall_ms;                  /* both sides, from the split to the result */
+    int32_t host_threads;
+    int32_t reserved;
+} cstm_share_stats;
+cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, int32_t host_threads,
+                                  uint64_t* count_out, cstm_share_stats* st, void* stream);
+
 /* ---------------------------------------------------------------- serving
  *
  * A request loop over one resident graph (the serving form of the method:

@@ -811,6 +811,7 @@ double cstm_cst_workload_run(cstm_cst* c) {
     HIP_TRY(hipStreamSynchronize(s));
     double w = 0.0;
     for (double x : h) w += x;  // in candidate order: the same result every time
+    c->root_w = std::move(h);
     return c->workload = w;
 }
 

@@ -630,14 +630,15 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     }
 }
 
-// Initial tasks: runs of root candidates of every query.
-__global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t* __restrict__ nroot,
-                       const int64_t* __restrict__ chunk, const int32_t* __restrict__ perm, int nq,
-                       unsigned long long total) {
+// Initial tasks: every seeding segment (a query and a run [lo, hi) of its
+// root candidates) cut into tasks of chunk[i] root candidates.
+__global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t* __restrict__ seg_lo,
+                       const int64_t* __restrict__ seg_hi, const int64_t* __restrict__ chunk,
+                       const int32_t* __restrict__ seg_q, int ns, unsigned long long total) {
     unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     for (unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        // seeding position i: the last with first[i] <= t
-        int lo = 0, hi = nq - 1;
+        // segment i: the last with first[i] <= t
+        int lo = 0, hi = ns - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if ((long long)t >= first[mid]) lo = mid;
@@ -646,10 +647,10 @@ __global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t
         const int i = lo;
         const int64_t r = (int64_t)t - first[i];
         GTask& T = A.tasks[t & A.qmask];
-        T.q = perm[i];
+        T.q = seg_q[i];
         T.depth = 0;
-        T.lo = r * chunk[i];
-        T.hi = T.lo + chunk[i] < nroot[i] ? T.lo + chunk[i] : nroot[i];
+        T.lo = seg_lo[i] + r * chunk[i];
+        T.hi = T.lo + chunk[i] < seg_hi[i] ? T.lo + chunk[i] : seg_hi[i];
         for (int p = 0; p < CSTM_MAX_K; ++p) T.prefix[p] = 0;
         A.ready[t & A.qmask] = (unsigned int)((t >> A.qlog) + 1);
     }
@@ -673,17 +674,43 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         for (int q = 0; q < nq; ++q) w[q] = cstm_cst_workload_run(csts[q]);
         std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
     }
-    // per seeding position: the first task, root candidates and roots per task
-    std::vector<int64_t> first(nq + 1, 0), nroot(nq, 0), chunk(nq, 1);
-    for (int i = 0; i < nq; ++i) {
-        const cstm_cst* c = csts[perm[i]];
-        nroot[i] = c->empty ? 0 : c->host_desc.pos[0].n;
-        // one root candidate per task unless the batch would fill half the ring
-        int64_t per = std::max<int64_t>(1, (nroot[i] * 2 * std::max(1, nq) + (int64_t)qcap - 1) / (int64_t)qcap);
-        chunk[i] = per;
-        first[i + 1] = first[i] + (nroot[i] + per - 1) / per;
+    // seeding segments, in seeding order: all root candidates of each query,
+    // or the caller's runs of them for a one-query call
+    struct Seg {
+        int32_t q;
+        int64_t lo, hi;
+    };
+    std::vector<Seg> segs;
+    if (nq == 1 && o.root_ranges) {
+        const int64_t nr = csts[0]->empty ? 0 : csts[0]->host_desc.pos[0].n;
+        for (int64_t i = 0; i < o.n_ranges; ++i) {
+            const int64_t lo = o.root_ranges[2 * i], hi = o.root_ranges[2 * i + 1];
+            CSTM_REQUIRE(0 <= lo && lo <= hi && hi <= nr, CSTM_EINVAL, "root range out of bounds");
+            if (hi > lo) segs.push_back({0, lo, hi});
+        }
+    } else {
+        for (int i = 0; i < nq; ++i) {
+            const cstm_cst* c = csts[perm[i]];
+            segs.push_back({perm[i], 0, c->empty ? 0 : (int64_t)c->host_desc.pos[0].n});
+        }
     }
-    const unsigned long long total = (unsigned long long)first[nq];
+    const int ns = (int)segs.size();
+    CSTM_REQUIRE(ns < (int)(qcap / 8), CSTM_EINVAL, "too many root ranges");
+    // per segment: the first task and the roots per task (one root candidate
+    // per task unless the batch would fill a quarter / half of the ring)
+    const int64_t fill = o.root_ranges ? 4 : 2;
+    std::vector<int64_t> first(ns + 1, 0), seg_lo(ns), seg_hi(ns), chunk(ns, 1);
+    std::vector<int32_t> seg_q(ns);
+    for (int i = 0; i < ns; ++i) {
+        const int64_t len = segs[i].hi - segs[i].lo;
+        const int64_t per = std::max<int64_t>(1, (len * fill * std::max(1, ns) + (int64_t)qcap - 1) / (int64_t)qcap);
+        seg_lo[i] = segs[i].lo;
+        seg_hi[i] = segs[i].hi;
+        seg_q[i] = segs[i].q;
+        chunk[i] = per;
+        first[i + 1] = first[i] + (len + per - 1) / per;
+    }
+    const unsigned long long total = (unsigned long long)first[ns];
     CSTM_REQUIRE(total < qcap / 2, CSTM_EINVAL, "too many root candidates for the task ring");
     if (total == 0) return;
     // workspace lent by the context for this launch, every region 256-byte aligned and sized by sizeof():
@@ -694,9 +721,9 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const size_t off_work = up(off_qu + sizeof(GQueue));
     const size_t off_desc = up(off_work + 8 * sizeof(unsigned long long));
     const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
-    const size_t off_slot = up(off_meta + (3 * (size_t)nq + 1) * sizeof(int64_t));
-    const size_t off_perm = up(off_slot + (size_t)nq * sizeof(int32_t));
-    const size_t off_lim = up(off_perm + (size_t)nq * sizeof(int32_t));
+    const size_t off_slot = up(off_meta + (4 * (size_t)ns + 1) * sizeof(int64_t));
+    const size_t off_segq = up(off_slot + (size_t)nq * sizeof(int32_t));
+    const size_t off_lim = up(off_segq + (size_t)ns * sizeof(int32_t));
     const size_t off_stop = up(off_lim + (size_t)nq * sizeof(unsigned long long));
     const size_t need = up(off_stop + (size_t)nq * sizeof(unsigned int));
     const size_t ready_b = qcap * sizeof(unsigned int);
@@ -713,7 +740,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     CstDev* descs = (CstDev*)(ws + off_desc);
     int64_t* meta = (int64_t*)(ws + off_meta);
     int32_t* dslot = (int32_t*)(ws + off_slot);
-    int32_t* dperm = (int32_t*)(ws + off_perm);
+    int32_t* dsegq = (int32_t*)(ws + off_segq);
     unsigned long long* dlim = (unsigned long long*)(ws + off_lim);
     unsigned int* dstop = (unsigned int*)(ws + off_stop);
     bool any_limit = false;
@@ -736,11 +763,12 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     init.tail.v = total;
     init.outstanding.v = total;
     HIP_TRY(hipMemcpyAsync(qu, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(meta, first.data(), (nq + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(meta + nq + 1, nroot.data(), nq * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(meta + 2 * nq + 1, chunk.data(), nq * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta, first.data(), (ns + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta + ns + 1, seg_lo.data(), ns * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta + 2 * ns + 1, seg_hi.data(), ns * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(meta + 3 * ns + 1, chunk.data(), ns * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(dslot, slot, nq * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dperm, perm.data(), nq * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dsegq, seg_q.data(), ns * 4, hipMemcpyHostToDevice, s));
     GArgs A;
     A.descs = descs;
     A.slot = dslot;
@@ -769,8 +797,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.flat_max = ctx->tune.hbm_flat_max;  // negative: never flatten
     A.donate_last_min = ctx->tune.hbm_donate_last_min;
     A.last_sum = ctx->tune.last_level_sum;
-    k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + nq + 1, meta + 2 * nq + 1, dperm,
-                                                                  nq, total);
+    k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + ns + 1, meta + 2 * ns + 1,
+                                                                  meta + 3 * ns + 1, dsegq, ns, total);
     HIP_TRY(hipGetLastError());
     hipEvent_t ev[2];
     HIP_TRY(hipEventCreate(&ev[0]));

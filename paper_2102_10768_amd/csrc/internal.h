@@ -271,6 +271,7 @@ struct cstm_cst {
     bool empty = false;  // some candidate set is empty: no embedding
     double t_build = 0, t_part = 0, t_enum = 0;
     double workload = -1;  // W_CST of the workload DP (Section V-C), computed on first use
+    std::vector<double> root_w;  // c_root(v) for every root candidate, with workload
 };
 
 // ---------------------------------------------------------------- helpers shared across files
@@ -295,6 +296,10 @@ bool cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list, uint64
 struct EnumOpts {
     const uint64_t* limits = nullptr;  // per CST of the call: stop once it has this many embeddings (0: all)
     int64_t deadline_ms = 0;           // stop the launch after this long (0: no limit)
+    // one-CST calls only: enumerate just these runs of root candidates, as
+    // [lo, hi) index pairs (nullptr: all of them); forces the HBM-resident kernel
+    const int64_t* root_ranges = nullptr;
+    int64_t n_ranges = 0;
 };
 void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                             uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,

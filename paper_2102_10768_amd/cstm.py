@@ -66,6 +66,24 @@ class cstm_enum_stats(ctypes.Structure):
     ]
 
 
+class cstm_share_stats(ctypes.Structure):
+    _fields_ = [
+        ("delta", ctypes.c_double),
+        ("w_host", ctypes.c_double),
+        ("w_device", ctypes.c_double),
+        ("groups_host", ctypes.c_int64),
+        ("groups_device", ctypes.c_int64),
+        ("count_host", ctypes.c_uint64),
+        ("count_device", ctypes.c_uint64),
+        ("copy_ms", ctypes.c_double),
+        ("host_ms", ctypes.c_double),
+        ("device_ms", ctypes.c_double),
+        ("wall_ms", ctypes.c_double),
+        ("host_threads", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class cstm_request_result(ctypes.Structure):
     _fields_ = [
         ("done", ctypes.c_int32),
@@ -123,7 +141,7 @@ EXPORTS = [
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
     "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
     "cstm_server_create", "cstm_server_submit", "cstm_server_poll", "cstm_server_wait", "cstm_server_get_stats",
-    "cstm_server_destroy", "cstm_cst_workload", "cstm_cst_build_ordered",
+    "cstm_server_destroy", "cstm_cst_workload", "cstm_cst_build_ordered", "cstm_enumerate_shared",
 ]
 
 _lib = None
@@ -174,6 +192,8 @@ def load_library():
         "cstm_server_destroy": (None, [P]),
         "cstm_cst_workload": (st, [P, ctypes.POINTER(ctypes.c_double)]),
         "cstm_cst_build_ordered": (st, [P, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]),
+        "cstm_enumerate_shared": (st, [P, ctypes.c_double, I64, I32, ctypes.POINTER(U64),
+                                       ctypes.POINTER(cstm_share_stats), P]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -374,6 +394,15 @@ class CST:
         w = ctypes.c_double()
         _check(load_library().cstm_cst_workload(self.handle, ctypes.byref(w)))
         return w.value
+
+    def count_shared(self, delta: float, n_runs: int = 0, host_threads: int = 0, stream=None):
+        """Algorithm 3: count with a share of at most ``delta`` of W_CST on the
+        host cores and the rest on the GPU.  Returns (count, stats dict)."""
+        c = ctypes.c_uint64()
+        st = cstm_share_stats()
+        _check(load_library().cstm_enumerate_shared(self.handle, float(delta), int(n_runs), int(host_threads),
+                                                    ctypes.byref(c), ctypes.byref(st), _stream_ptr(stream)))
+        return int(c.value), {name: getattr(st, name) for name, _ in cstm_share_stats._fields_ if name != "reserved"}
 
     def info(self) -> dict:
         i = cstm_cst_info()
