@@ -16,7 +16,12 @@ Prints one JSON line (see the keys below); exits 1 if a count is wrong.
     python bench.py --workload c2 --share 0,0.01,0.1 [--host-threads 16]
 
 sweeps the host-core share of Algorithm 3 instead (CSTs built beforehand, one
-JSON line per delta, counts checked).
+JSON line per delta, counts checked), and
+
+    python bench.py --workload c2 --orders 6
+
+times each query under its path-based order and random tree orders (Section
+VII-C's BEST/AVG/WORST).
 """
 
 from __future__ import annotations
@@ -85,6 +90,7 @@ def main():
     ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
     ap.add_argument("--share", default="", help="comma-separated deltas: sweep the host-core share (Algorithm 3)")
     ap.add_argument("--host-threads", type=int, default=0, help="--share: host threads (0: the host's cores, <= 16)")
+    ap.add_argument("--orders", type=int, default=0, help="matching-order study: random tree orders per query")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
@@ -111,6 +117,8 @@ def main():
         return serve_main(a, W, g, queries, expected)
     if a.share:
         return share_main(a, W, g, queries, expected)
+    if a.orders:
+        return orders_main(a, W, g, queries, expected)
 
     mode_id = {"auto": 0, "lds": 1, "hbm": 2}[a.mode]
     ctx = cstm.Context(0, tune={"enum_mode": mode_id, "collect_stats": 0})
@@ -367,6 +375,68 @@ def share_main(a, W, g, queries, expected):
               flush=True)
     for c in csts:
         c.close()
+    G.close()
+    ctx.close()
+
+
+def orders_main(a, W, g, queries, expected):
+    """Matching-order study (Section VII-C): per query, the enumeration kernel
+    time under the path-based order and under a.orders random orders that
+    start at the CST root and follow the BFS tree (seeded); counts checked, a
+    2 s deadline per run (INF beyond it).  One JSON line with BEST/AVG/WORST."""
+    import numpy as np
+    import torch
+
+    from paper_2102_10768_amd import cstm
+
+    ctx = cstm.Context(0, tune={"enum_mode": 2, "collect_stats": 0})
+    G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
+                   torch.from_numpy(g.label).cuda())
+    rng = np.random.default_rng(5)
+    deadline_s = 2.0
+    per = []
+    for i, (q, want) in enumerate(zip(queries, expected)):
+        c = cstm.CST(ctx, G, q.qlabel, q.qedges)
+        info = c.info()
+        c.count()
+        if c.count() != want:
+            raise SystemExit(f"count mismatch on query {i}")
+        t_def = ctx.last_enum_stats()["kernel_ms"]
+        c.close()
+        times = []
+        for _ in range(a.orders):
+            order, placed = [info["root"]], {info["root"]}
+            while len(order) < q.k:
+                ready = [u for u in range(q.k) if u not in placed and info["parent"][u] in placed]
+                u = int(rng.choice(ready))
+                order.append(u)
+                placed.add(u)
+            c = cstm.CST(ctx, G, q.qlabel, q.qedges, order=order)
+            try:
+                c.count(deadline_s=deadline_s)
+                if c.count(deadline_s=deadline_s) != want:
+                    raise SystemExit(f"count mismatch on query {i} under order {order}")
+                times.append(ctx.last_enum_stats()["kernel_ms"])
+            except cstm.CstmError as e:
+                if e.status != cstm.ETIMEOUT:
+                    raise
+                times.append(float("inf"))
+            c.close()
+        per.append((t_def, times))
+        print(f"query {i} k={q.k}: path order {t_def:.2f} ms, random orders {min(times):.2f}..{max(times):.2f} ms",
+              file=sys.stderr, flush=True)
+    cap = deadline_s * 1e3
+    fin = [[t for t in ts if t != float("inf")] for _, ts in per]
+    print(json.dumps({
+        "workload": a.workload, "queries": len(per), "orders_per_query": a.orders, "deadline_ms": cap,
+        "path_order_ms": sum(t for t, _ in per),
+        "best_ms": sum(min(ts) for _, ts in per),
+        "avg_ms": sum(float(np.mean(f)) if f else cap for f in fin),
+        "worst_ms": sum(min(max(ts), cap) for _, ts in per),
+        "inf_runs": sum(t == float("inf") for _, ts in per for t in ts),
+        "worst_over_best_median": float(np.median([min(max(ts), cap) / max(min(ts), 1e-6) for _, ts in per])),
+        "path_within_10pct_of_best": sum(t <= 1.1 * min(ts) for t, ts in per),
+    }), flush=True)
     G.close()
     ctx.close()
 
