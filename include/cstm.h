@@ -108,8 +108,9 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      cstm_enum_stats.summed).  1 (default): on; negative:
  *                      off.  Listing always visits every candidate.
  *   batch_order        HBM mode, several CSTs in one launch: 0 (default)
- *                      seeds the heaviest first by W_CST (cstm_cst_workload);
- *                      negative: in the order given.                         */
+ *                      or negative seeds them in the order given; positive
+ *                      seeds the heaviest first by W_CST (cstm_cst_workload,
+ *                      one workload DP per CST not yet weighed).             */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2

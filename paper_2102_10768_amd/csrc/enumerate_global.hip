@@ -665,11 +665,11 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
                                const EnumOpts& o, cstm_enum_stats* st, hipStream_t s) {
     const int qlog = 20;
     const unsigned long long qcap = 1ull << qlog;
-    // seeding order: the heaviest queries (largest W_CST, Section V-C) first, so
-    // the long searches start early and the short ones fill in behind them
+    // seeding order: as given, or (batch_order > 0) the heaviest queries
+    // (largest W_CST, Section V-C) first, so the long searches start early
     std::vector<int32_t> perm(nq);
     for (int q = 0; q < nq; ++q) perm[q] = q;
-    if (nq > 1 && ctx->tune.batch_order >= 0) {
+    if (nq > 1 && ctx->tune.batch_order > 0) {
         std::vector<double> w(nq);
         for (int q = 0; q < nq; ++q) w[q] = cstm_cst_workload_run(csts[q]);
         std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });

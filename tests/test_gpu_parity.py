@@ -266,10 +266,10 @@ def test_batch_seeding_order_does_not_change_counts():
 
     qs = query_set(g, [3, 4, 5, 6] * 4, 73)
     csts = [cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges) for q in qs]
-    by_w = cstm.batch_count(ctx("hbm"), csts)
-    ctx("hbm").tune = {"batch_order": -1}
+    given = cstm.batch_count(ctx("hbm"), csts)
+    ctx("hbm").tune = {"batch_order": 1}
     try:
-        given = cstm.batch_count(ctx("hbm"), csts)
+        by_w = cstm.batch_count(ctx("hbm"), csts)
     finally:
         ctx("hbm").tune = {"batch_order": 0}
     alone = [c.count() for c in csts]
