@@ -405,14 +405,16 @@ static unsigned tile_grid(int64_t total) {
 
 // The lists of `from` (a query vertex) into `to`, using to's rank table.
 // Scratch: deg, rowoff and cnt hold at least #C(from) + 1 int64 entries.
+// The longest list goes to the device int *d_max (zeroed by the caller), read
+// back once after all lists; blocks the fill kernel still uses go to `later`,
+// released after the build's last wait.
 static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, EdgeLists& el, int* d_max,
-                        int64_t* deg, int64_t* rowoff, int64_t* cnt, bool with_gid) {
+                        int64_t* deg, int64_t* rowoff, int64_t* cnt, bool with_gid, std::vector<void*>& later) {
     const cstm_graph* g = c->g;
     hipStream_t s = c->stream;
     const int64_t np = c->ncand[from];
     uint64_t key = (uint64_t)c->qlabel[to] << 32;
     el.off = c->mem.get_n<int64_t>(np + 1);
-    HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int), s));
     const Rows R = flat_rows(c, c->cand[from], np, deg, rowoff);
     const int64_t ntiles = (R.total + kTile - 1) / kTile;
     int64_t* tile_cnt = c->mem.get_n<int64_t>(ntiles + 1);
@@ -436,11 +438,9 @@ static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, Edge
         k_list_fill<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank, key, c->cnt0[to],
                                                               loc[to], tile_base, el.adj, el.adj_gid);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamSynchronize(s));
-        c->mem.release(tile_base);
+        later.push_back(tile_base);
     }
-    HIP_TRY(hipMemcpyAsync(&el.max_len, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // the last reader of tile_cnt was the scan above, which waited for the stream
     c->mem.release(tile_cnt);
 }
 
@@ -555,8 +555,11 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         c->mem.release(frow);
     }
 
-    // 4a. tree lists
-    int* d_max = c->mem.get_n<int>(1);
+    // 4a. tree lists (longest-list slots: tree edges by child, then non-tree edges)
+    const int n_slots = k + (int)c->nontree.size();
+    int* d_max = c->mem.get_n<int>(n_slots);
+    HIP_TRY(hipMemsetAsync(d_max, 0, (size_t)n_slots * sizeof(int), s));
+    std::vector<void*> later;
     int64_t maxn = 1;
     for (int u = 0; u < k; ++u) maxn = std::max(maxn, c->ncand[u]);
     int64_t* d_cnt = c->mem.get_n<int64_t>(maxn + 1);
@@ -565,8 +568,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     if (!c->empty) {
         for (int t = 1; t < k; ++t) {
             int u = c->bfs[t];
-            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max, l_deg, l_row, d_cnt, false);
-            c->d_cst = std::max(c->d_cst, c->tree[u].max_len);
+            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max + u, l_deg, l_row, d_cnt, false, later);
         }
     }
     // 4b. matching order: the caller's (checked against the tree) or the path-based one
@@ -632,19 +634,36 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
     }
     // 4c. non-tree candidate edges, earlier -> later in the order
-    for (auto& e : c->nontree) {
-        int a = e.first, b = e.second;
+    for (size_t j = 0; j < c->nontree.size(); ++j) {
+        int a = c->nontree[j].first, b = c->nontree[j].second;
         if (c->pos_of[a] > c->pos_of[b]) std::swap(a, b);
         EdgeLists el;
         el.from = c->pos_of[a];
         el.to = c->pos_of[b];
         if (!c->empty) {
-            build_lists(c, a, b, loc, el, d_max, l_deg, l_row, d_cnt, true);
-            c->d_cst = std::max(c->d_cst, el.max_len);
+            build_lists(c, a, b, loc, el, d_max + k + (int)j, l_deg, l_row, d_cnt, true, later);
         } else {
             el.off = nullptr;
         }
         c->nt.push_back(el);
+    }
+    // longest lists: one read-back for every edge (also the wait for the fills)
+    {
+        std::vector<int> h((size_t)n_slots, 0);
+        HIP_TRY(hipMemcpyAsync(h.data(), d_max, (size_t)n_slots * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!c->empty) {
+            for (int t = 1; t < k; ++t) {
+                const int u = c->bfs[t];
+                c->tree[u].max_len = h[(size_t)u];
+                c->d_cst = std::max(c->d_cst, c->tree[u].max_len);
+            }
+            for (size_t j = 0; j < c->nt.size(); ++j) {
+                c->nt[j].max_len = h[(size_t)k + j];
+                c->d_cst = std::max(c->d_cst, c->nt[j].max_len);
+            }
+        }
+        for (void* p : later) c->mem.release(p);
     }
     std::sort(c->nt.begin(), c->nt.end(), [](const EdgeLists& x, const EdgeLists& y) {
         return x.to != y.to ? x.to < y.to : x.from < y.from;
