@@ -248,7 +248,8 @@ cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max
  * the tree-shaped paths the CST holds: an upper bound on the embeddings, equal
  * to their number for tree queries with pairwise-distinct labels.  Computed on
  * the device in double precision (exact below 2^53) and cached in the CST;
- * batched launches use it to start the heaviest queries first. */
+ * batched launches seed the heaviest queries first by it when
+ * tune.batch_order > 0, and cstm_enumerate_shared splits work by it. */
 cstm_status cstm_cst_workload(cstm_cst* cst, double* w_out);
 
 cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
