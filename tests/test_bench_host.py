@@ -49,3 +49,31 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path):
     assert b.measured_traffic("c2") is None
     os.remove(tmp_path / prof)
     assert b.measured_traffic("c2") is None
+
+
+def _st(mode, ms, N=0, M=0, F=0, summed=0, image_bytes=0):
+    return {"mode": mode, "kernel_ms": ms, "launches": 1, "extensions": N, "edge_checks": M, "pushed": F,
+            "summed": summed, "image_bytes": image_bytes}
+
+
+def test_roofline_prices_the_dominant_kernel():
+    b = _bench()
+    # device-memory mode only: CST bytes + 4 per read candidate + 4 per check + 8 per push
+    timed = [_st(2, 10.0), _st(2, 30.0)]
+    counted = [({"bytes": 1000}, _st(2, 0, N=100, M=10, F=5, summed=40)),
+               ({"bytes": 3000}, _st(2, 0, N=50, M=0, F=1))]
+    r = b.roofline_of(timed, counted)
+    alg = 1000 + 3000 + 4 * (150 - 40) + 4 * 10 + 8 * 6
+    assert r["kernel"] == "k_enumerate_global" and r["algorithmic_bytes_per_step"] == alg
+    assert abs(r["achieved"] - alg / 0.040 / 1e9) < 1e-12
+    assert r["launches_per_step"] == 2 and abs(r["avg_launch_ms"] - 20.0) < 1e-12
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15 and "on_chip" not in r
+    # LDS images dominate: HBM bytes are the images, the list work is on chip
+    timed = [_st(1, 50.0), _st(2, 5.0)]
+    counted = [({"bytes": 1000}, _st(1, 0, N=100, M=10, F=5, image_bytes=7000)),
+               ({"bytes": 3000}, _st(2, 0, N=50))]
+    r = b.roofline_of(timed, counted)
+    assert r["kernel"] == "k_enumerate" and r["algorithmic_bytes_per_step"] == 7000
+    assert r["on_chip"]["bytes_per_step"] == 4 * 100 + 4 * 10 + 8 * 5
+    assert abs(r["on_chip"]["peak"] - 128 * 256 * 2.4) < 1e-9
+    assert b.roofline_of([], [])["achieved"] == 0.0
