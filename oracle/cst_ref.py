@@ -9,6 +9,8 @@ The count oracle (``oracle.c``) fixes *what* is computed; this module restates
 * :func:`path_order` -- the path-based matching order of Section V-B.
 * :func:`partition` -- the CST partition of Algorithm 2 (Section V-B).
 * :func:`workload` -- the workload estimate c_u(v) / W_CST of Section V-C.
+* :func:`share_split` -- Algorithm 3's host/accelerator split of the work
+  (Section V-C), over runs of root candidates.
 * :func:`fast_round` -- one Generator / Visited Validator / Edge Validator /
   Synchronizer round (Algorithms 5-8, Section VI-A), for the worked example.
 * :func:`enumerate_cst` -- all embeddings found by traversing only the CST
@@ -276,6 +278,37 @@ def workload(cst: CST, cand_override=None):
             c[u][v] = val
     W = sum(c[cst.root].values())
     return c, W
+
+
+def share_split(weights, delta: float, n_runs: int):
+    """Algorithm 3 (Section V-C): hand each unit of work to the host or the
+    accelerator so that the host's share of the workload stays below delta.
+
+    Reading: the units are runs of consecutive root candidates (the first
+    split of Algorithm 2); run i of R covers root indices [i*n//R, (i+1)*n//R)
+    and weighs the sum of c_root over them (``weights`` in root-candidate
+    order).  Units are decided in order: to the host when
+    W_C + W < delta * (W_C + W_F + W), else to the accelerator; W_C or W_F
+    then grows by W.  Sums are taken as floats, run by run in root order.
+
+    Returns (host_runs, device_runs, W_C, W_F), runs as (lo, hi) pairs.
+    """
+    n = len(weights)
+    runs = min(n, n_runs if n_runs > 0 else 1024)
+    host, dev = [], []
+    wc = wf = 0.0
+    for i in range(runs):
+        lo, hi = i * n // runs, (i + 1) * n // runs
+        w = 0.0
+        for r in range(lo, hi):
+            w += float(weights[r])
+        if wc + w < delta * (wc + wf + w):
+            host.append((lo, hi))
+            wc += w
+        else:
+            dev.append((lo, hi))
+            wf += w
+    return host, dev, wc, wf
 
 
 # ---------------------------------------------------------------- partition (Algorithm 2)

@@ -176,3 +176,46 @@ def test_partitions_are_disjoint_complete_and_within_budget(seed):
         seen += cst_ref.enumerate_cst(cst, order, sets)
     assert len(seen) == len(set(seen))
     assert sorted(seen) == full
+
+
+def test_share_split_on_the_worked_example():
+    """Algorithm 3 on the workload example: c(v1) = 4, c(v2) = 3, one run per
+    root candidate.  By the rule: v1 goes to the accelerator (4 < 4*delta never
+    holds for delta <= 1), then v2 goes to the host iff 3 < 7*delta."""
+    g, q, _ = fig4()
+    cst = cst_ref.build_cst(g, q.qlabel, q.qedges)
+    c, W = cst_ref.workload(cst)
+    weights = [c[cst.root][v] for v in cst.cand[cst.root]]
+    assert sorted(weights) == [3, 4] and W == 7
+    second = weights[1]  # the first run always goes to the accelerator
+    for delta in (0.0, 0.4, 3 / 7, 0.43, 0.5, 4 / 7, 0.58, 1.0):
+        host, dev, wc, wf = cst_ref.share_split(weights, delta, 2)
+        assert dev[0] == (0, 1)
+        # by hand: 0 + second < delta * (0 + first + second) = 7 * delta
+        assert (host == [(1, 2)]) == (second < 7 * delta)
+        assert wc + wf == 7.0
+    if second == 3:
+        assert cst_ref.share_split(weights, 0.43, 2)[0] == [(1, 2)]
+        assert cst_ref.share_split(weights, 3 / 7, 2)[0] == []
+    # one run holding both: never the host's (W < delta*W fails for delta <= 1)
+    assert cst_ref.share_split(weights, 1.0, 1) == ([], [(0, 2)], 0.0, 7.0)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_share_split_keeps_the_host_share_below_delta(seed):
+    rng = np.random.default_rng(900 + seed)
+    w = rng.integers(0, 1000, size=int(rng.integers(1, 300))).tolist()
+    for delta in (0.0, 0.01, 0.1, 0.5, 0.9, 1.0):
+        for runs in (0, 1, 3, 17, 1000):
+            host, dev, wc, wf = cst_ref.share_split(w, delta, runs)
+            # runs tile the root candidates in order, each exactly once
+            tiles = sorted(host + dev)
+            assert tiles[0][0] == 0 and tiles[-1][1] == len(w)
+            assert all(a[1] == b[0] and a[0] < a[1] for a, b in zip(tiles, tiles[1:]))
+            assert len(tiles) == min(len(w), runs if runs > 0 else 1024)
+            assert wc + wf == float(sum(w))
+            assert wc == sum(sum(w[lo:hi]) for lo, hi in host)
+            if delta == 0.0:
+                assert host == []
+            if host:
+                assert wc < delta * (wc + wf)

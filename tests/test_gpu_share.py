@@ -14,6 +14,7 @@ import pytest
 
 import closed_forms as cf
 import oracle
+from oracle import cst_ref
 from gpu_common import ctx, gpu_graph
 from synth import make_graph, query_set
 from test_oracle import random_connected_query, random_tiny_graph
@@ -105,3 +106,28 @@ def test_shared_rejects_bad_arguments():
     # the CST still counts normally afterwards
     assert c.count() == oracle.count(g, q)
     c.close()
+
+
+def test_split_equals_the_reference_rule():
+    """The runs each side receives and W_C, W_F equal the reference
+    restatement of Algorithm 3 on the reference DP's c_root values."""
+    from paper_2102_10768_amd import cstm
+
+    g = _c1()
+    G = gpu_graph(g, "hbm")
+    for q in query_set(g, [4, 5, 6, 7], 213):
+        ref = cst_ref.build_cst(g, q.qlabel, q.qedges)
+        cmap, W = cst_ref.workload(ref)
+        c = cstm.CST(ctx("hbm"), G, q.qlabel, q.qedges)
+        assert c.info()["root"] == ref.root
+        roots = c.candidates(ref.root).tolist()
+        assert roots == ref.cand[ref.root]
+        weights = [cmap[ref.root].get(v, 0) for v in roots]
+        assert c.workload() == float(W)
+        for delta in (0.05, 0.3, 0.7):
+            for runs in (0, 3, 11):
+                _, st = c.count_shared(delta, n_runs=runs, host_threads=2)
+                host, dev, wc, wf = cst_ref.share_split(weights, delta, runs)
+                assert (st["groups_host"], st["groups_device"]) == (len(host), len(dev)), (q.k, delta, runs)
+                assert (st["w_host"], st["w_device"]) == (wc, wf)
+        c.close()
