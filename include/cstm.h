@@ -110,7 +110,13 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *   batch_order        HBM mode, several CSTs in one launch: 0 (default)
  *                      or negative seeds them in the order given; positive
  *                      seeds the heaviest first by W_CST (cstm_cst_workload,
- *                      one workload DP per CST not yet weighed).             */
+ *                      one workload DP per CST not yet weighed).
+ *   hbm_idle_ms        HBM mode: a safety net.  Busy wavefronts refresh a
+ *                      progress beat about once a millisecond; a launch in
+ *                      which idle wavefronts see neither a task nor a beat for
+ *                      this many milliseconds stops with CSTM_EDEVICE
+ *                      (default 30000).  A deadline that passes first is
+ *                      reported as CSTM_ETIMEOUT.                            */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -130,6 +136,7 @@ typedef struct {
     int32_t last_level_sum;
     int32_t hbm_donate_min;
     int32_t batch_order;
+    int32_t hbm_idle_ms;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).
@@ -220,7 +227,7 @@ cstm_status cstm_cst_build_ordered(cstm_ctx* ctx, const cstm_graph* g, int32_t k
                                    cstm_cst** out);
 
 /* Upper bound on the device bytes cstm_cst_build requests for the query
- * (k, qlabel, m_q, qedges as for cstm_cst_build): the CST of Section IV-A plus
+ * (k, qlabel, m_q, qedges as for cstm_cst_build): the CST of Section V-A plus
  * its build-time tables, from the label index alone.  #C(u) is at most the
  * number of vertices passing the label and degree filter, and a candidate edge
  * list holds each data edge at most once, so the summed degrees of either
@@ -247,10 +254,11 @@ cstm_status cstm_cst_partition(cstm_cst* cst, uint64_t budget_bytes, int32_t max
  * the leaves), W_CST = sum of c_root over the root's candidates.  It counts
  * the tree-shaped paths the CST holds: an upper bound on the embeddings, equal
  * to their number for tree queries with pairwise-distinct labels.  Computed on
- * the device in double precision (exact below 2^53) and cached in the CST;
- * batched launches seed the heaviest queries first by it when
- * tune.batch_order > 0, and cstm_enumerate_shared splits work by it. */
-cstm_status cstm_cst_workload(cstm_cst* cst, double* w_out);
+ * the device in unsigned 64-bit integers that saturate: *w_out is exactly
+ * min(W_CST, 2^64 - 1), and so is every c_root(v) the host share uses.
+ * Cached in the CST; batched launches seed the heaviest queries first by it
+ * when tune.batch_order > 0, and cstm_enumerate_shared splits work by it. */
+cstm_status cstm_cst_workload(cstm_cst* cst, uint64_t* w_out);
 
 cstm_status cstm_cst_info_get(const cstm_cst* cst, cstm_cst_info* out);
 
@@ -301,7 +309,7 @@ cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* cst
  * n_runs or host_threads outside [0, 256]. */
 typedef struct cstm_share_stats {
     double delta;
-    double w_host, w_device;         /* W_C and W_F after the last run */
+    uint64_t w_host, w_device;       /* W_C and W_F after the last run (saturating at 2^64 - 1) */
     int64_t groups_host, groups_device;  /* runs each side received */
     uint64_t count_host, count_device;
     double copy_ms;                  /* until the host copy of the lists was complete */

@@ -56,6 +56,8 @@ def _load():
             p, p, p, p,  # count, nodes, rows_written, threads_used
         ]
         lib.oracle_num_cores.restype = ctypes.c_int
+        lib.oracle_label_group.restype = ctypes.c_int
+        lib.oracle_label_group.argtypes = [ctypes.c_int64, p, p, p, p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -78,11 +80,27 @@ class MatchResult:
         return f"MatchResult(status={self.status}, count={self.count}, nodes={self.nodes}, threads={self.threads})"
 
 
-def label_grouped_col(g) -> np.ndarray:
+def label_grouped_col(g, threads: int = 0) -> np.ndarray:
     """G's rows regrouped by (neighbour label, neighbour id), same row_ptr.
 
     Passing it to :func:`match` lets the matcher visit only the neighbours of
-    the label it needs; the result is the same."""
+    the label it needs; the result is the same.  Computed by ``oracle.c``
+    (rows sorted independently on host threads), so it scales to
+    billion-edge graphs; :func:`label_grouped_col_numpy` is the plain form."""
+    lib = _load()
+    row_ptr = _c(g.row_ptr, np.int64)
+    col = _c(g.col, np.int32)
+    label = _c(g.label, np.int32)
+    out = np.empty_like(col)
+    st = lib.oracle_label_group(int(g.n), row_ptr.ctypes.data, col.ctypes.data, label.ctypes.data,
+                                out.ctypes.data, int(threads))
+    if st != OK:
+        raise MemoryError("label grouping ran out of host memory")
+    return out
+
+
+def label_grouped_col_numpy(g) -> np.ndarray:
+    """The same regrouping as :func:`label_grouped_col`, by one numpy stable sort."""
     row_ptr = np.asarray(g.row_ptr, dtype=np.int64)
     col = np.asarray(g.col, dtype=np.int32)
     label = np.asarray(g.label, dtype=np.int64)

@@ -23,7 +23,9 @@ function that takes it.  Everything works on plain Python sets and lists.
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -264,7 +266,7 @@ def enumerate_cst(cst: CST, order: list, cand_override=None) -> list:
 def workload(cst: CST, cand_override=None):
     """c_u(v) = prod over tree children u' of sum_{v' in N^u_{u'}(v)} c_{u'}(v'); W_CST = sum over root candidates.
 
-    Section V-C.  Leaves have c = 1.  Returns (c, W) with c[u][v].
+    Section V-C.  Leaves have c = 1.  Exact Python integers.  Returns (c, W) with c[u][v].
     """
     cand = [set(c) for c in (cand_override or cst.cand)]
     c = [dict() for _ in range(cst.k)]
@@ -280,35 +282,42 @@ def workload(cst: CST, cand_override=None):
     return c, W
 
 
+U64_MAX = (1 << 64) - 1
+
+
+def saturate_u64(x: int) -> int:
+    """min(x, 2^64 - 1): a value held in an unsigned 64-bit integer that saturates."""
+    return min(int(x), U64_MAX)
+
+
 def share_split(weights, delta: float, n_runs: int):
-    """Algorithm 3 (Section V-C): hand each unit of work to the host or the
-    accelerator so that the host's share of the workload stays below delta.
+    """Algorithm 3 (Section V-C): the host takes a unit of work only while its
+    share of the workload handed out so far, that unit included, stays below
+    delta; every other unit goes to the accelerator.
 
     Reading: the units are runs of consecutive root candidates (the first
     split of Algorithm 2); run i of R covers root indices [i*n//R, (i+1)*n//R)
-    and weighs the sum of c_root over them (``weights`` in root-candidate
-    order).  Units are decided in order: to the host when
-    W_C + W < delta * (W_C + W_F + W), else to the accelerator; W_C or W_F
-    then grows by W.  Sums are taken as floats, run by run in root order.
+    and weighs w_i, the sum of c_root over them (``weights`` in root-candidate
+    order).  With S_i = w_0 + ... + w_i (all work handed out once run i is)
+    and H the host's part of S_{i-1}, run i goes to the host exactly when
+    H + w_i < delta * S_i.  Integers are exact and delta is taken as the exact
+    rational value of the float.
 
     Returns (host_runs, device_runs, W_C, W_F), runs as (lo, hi) pairs.
     """
     n = len(weights)
-    runs = min(n, n_runs if n_runs > 0 else 1024)
-    host, dev = [], []
-    wc = wf = 0.0
-    for i in range(runs):
-        lo, hi = i * n // runs, (i + 1) * n // runs
-        w = 0.0
-        for r in range(lo, hi):
-            w += float(weights[r])
-        if wc + w < delta * (wc + wf + w):
-            host.append((lo, hi))
-            wc += w
-        else:
-            dev.append((lo, hi))
-            wf += w
-    return host, dev, wc, wf
+    R = min(n, n_runs if n_runs > 0 else 1024)
+    runs = [(i * n // R, (i + 1) * n // R) for i in range(R)]
+    w = [sum(int(x) for x in weights[lo:hi]) for lo, hi in runs]
+    d = Fraction(delta)
+    to_host = []
+    H = 0
+    for wi, Si in zip(w, itertools.accumulate(w)):
+        to_host.append(H + wi < d * Si)
+        H += wi if to_host[-1] else 0
+    host = [r for r, t in zip(runs, to_host) if t]
+    dev = [r for r, t in zip(runs, to_host) if not t]
+    return host, dev, H, sum(w) - H
 
 
 # ---------------------------------------------------------------- partition (Algorithm 2)
@@ -452,41 +461,45 @@ def partition(cst: CST, order: list, delta_s: int, delta_d: int = 1 << 30, force
 def fast_round(cst: CST, order: list, P: list, N_o: int, cand_override=None):
     """One Generator -> validators -> Synchronizer round on the partial results ``P``.
 
-    ``P`` holds partial results as tuples of data vertices in ``order``
-    positions, all of the same length n (the deepest level).  Returns
-    (P_o, T_v, T_n, B_v, B_n, survivors, rest): ``rest`` are inputs not
-    expanded because the round was full (they stay in P, reading of the
-    ``break``).  T_v entries are (v, index of p_i); T_n entries are
-    (M(u), M(u_n), index of p_o), in the order the Generator pushes them.
+    Section VI-A restated from what each stage computes.  ``P`` holds partial
+    results as tuples of data vertices in ``order`` positions, all of length n;
+    u = order[n] is the vertex the round maps, u_p its tree parent.
+
+    * The extensions of a partial result p are the candidates of u in the CST
+      list of p's u_p candidate (within the candidate sets in force).
+    * The round takes the longest prefix of P whose extensions together number
+      at most N_o (the Generator's output budget; reading of its cut: a partial
+      result whose extensions do not all fit stays in P for the next round).
+      P_o is those extensions in order; T_v pairs each new vertex with the
+      index (within the prefix) of the partial result it extends.
+    * The backward non-tree neighbours of u are its query neighbours other
+      than u_p and its tree children that are already mapped; T_n holds, for
+      each of them in ascending id and then for each p_o, the triple
+      (M(u), M(u_n), index of p_o).
+    * B_v(p_o) = 1 iff the new vertex is not among p_o's earlier vertices;
+      B_n(p_o) = 1 iff the CST joins the new vertex to the mapping of every
+      backward non-tree neighbour.  The survivors are the p_o with both bits.
+
+    Returns (P_o, T_v, T_n, B_v, B_n, survivors, rest), ``rest`` = P minus the
+    prefix taken.
     """
     cand = [set(c) for c in (cand_override or cst.cand)]
     n = len(P[0])
     u = order[n]
     up = cst.parent[u]
     pos = {w: i for i, w in enumerate(order)}
-    P_o, T_v = [], []
-    rest = list(P)
-    taken = 0
-    while rest:
-        p_i = rest[0]
-        cu = [v for v in cst.tree_adj[(up, u)].get(p_i[pos[up]], []) if v in cand[u]]
-        if len(P_o) + len(cu) > N_o:
-            break
-        rest.pop(0)
-        for v in cu:
-            T_v.append((v, taken))
-            P_o.append(p_i + (v,))
-        taken += 1
+
+    def extensions(p):
+        return [v for v in cst.tree_adj[(up, u)].get(p[pos[up]], []) if v in cand[u]]
+
+    ext = [extensions(p) for p in P]
+    fits = [total <= N_o for total in itertools.accumulate(len(e) for e in ext)]
+    taken = fits.index(False) if False in fits else len(P)
+    P_o = [P[i] + (v,) for i in range(taken) for v in ext[i]]
+    T_v = [(v, i) for i in range(taken) for v in ext[i]]
     back_nt = [un for un in cst.qadj[u] if un != up and cst.parent[un] != u and pos[un] < n]
-    T_n, which = [], []
-    for un in back_nt:
-        for j, p_o in enumerate(P_o):
-            T_n.append((p_o[n], p_o[pos[un]], j))
-            which.append(un)
-    B_v = [0 if p_o[n] in p_o[:n] else 1 for p_o in P_o]
-    B_n = [1] * len(P_o)
-    for (v, vn, j), un in zip(T_n, which):
-        if vn not in cst.nt_adj[(u, un)].get(v, []):
-            B_n[j] = 0
-    survivors = [p for j, p in enumerate(P_o) if B_v[j] and B_n[j]]
-    return P_o, T_v, T_n, B_v, B_n, survivors, rest
+    T_n = [(p_o[n], p_o[pos[un]], j) for un in back_nt for j, p_o in enumerate(P_o)]
+    B_v = [int(p_o[n] not in p_o[:n]) for p_o in P_o]
+    B_n = [int(all(p_o[pos[un]] in cst.nt_adj[(u, un)].get(p_o[n], []) for un in back_nt)) for p_o in P_o]
+    survivors = [p for p, bv, bn in zip(P_o, B_v, B_n) if bv and bn]
+    return P_o, T_v, T_n, B_v, B_n, survivors, list(P[taken:])

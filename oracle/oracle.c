@@ -374,3 +374,67 @@ int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const in
     free(ws); free(th); free(c->roots); free(c);
     return status;
 }
+
+/* ------------------------------------------------------------------ label-grouped rows
+ * The same rows as col, each reordered by (label of the entry, entry id): the
+ * optional lcol argument of oracle_match.  Rows are split over nthreads POSIX
+ * threads (0 = all online cores); each row is sorted on its own by a
+ * comparison sort of (label, id) pairs, so the result does not depend on the
+ * thread count.  Returns OR_OK or OR_ENOMEM. */
+typedef struct {
+    int64_t n;
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* lab;
+    int32_t* out;
+    _Atomic int64_t next;
+    _Atomic int oom;
+} group_t;
+
+static int pair_cmp(const void* a, const void* b) {
+    const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void* group_worker(void* arg) {
+    group_t* G = (group_t*)arg;
+    int64_t cap = 0;
+    int64_t* buf = NULL;
+    for (;;) {
+        const int64_t v0 = atomic_fetch_add(&G->next, 4096);
+        if (v0 >= G->n) break;
+        const int64_t v1 = v0 + 4096 < G->n ? v0 + 4096 : G->n;
+        for (int64_t v = v0; v < v1; ++v) {
+            const int64_t e0 = G->rp[v], d = G->rp[v + 1] - e0;
+            if (d > cap) {
+                int64_t* nb = (int64_t*)realloc(buf, (size_t)d * sizeof(int64_t));
+                if (!nb) { atomic_store(&G->oom, 1); free(buf); return NULL; }
+                buf = nb;
+                cap = d;
+            }
+            for (int64_t i = 0; i < d; ++i) {
+                const int32_t x = G->col[e0 + i];
+                buf[i] = ((int64_t)G->lab[x] << 32) | (int64_t)(uint32_t)x;
+            }
+            qsort(buf, (size_t)d, sizeof(int64_t), pair_cmp);
+            for (int64_t i = 0; i < d; ++i) G->out[e0 + i] = (int32_t)(uint32_t)buf[i];
+        }
+    }
+    free(buf);
+    return NULL;
+}
+
+int oracle_label_group(int64_t n, const int64_t* row_ptr, const int32_t* col, const int32_t* label, int32_t* out,
+                       int nthreads) {
+    group_t G;
+    G.n = n; G.rp = row_ptr; G.col = col; G.lab = label; G.out = out;
+    atomic_init(&G.next, 0);
+    atomic_init(&G.oom, 0);
+    int nt = nthreads > 0 ? nthreads : oracle_num_cores();
+    pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+    if (!th) return OR_ENOMEM;
+    for (int t = 0; t < nt; ++t) pthread_create(&th[t], NULL, group_worker, &G);
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+    free(th);
+    return atomic_load(&G.oom) ? OR_ENOMEM : OR_OK;
+}

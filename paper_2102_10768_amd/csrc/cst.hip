@@ -297,21 +297,28 @@ __global__ void k_sum_sat(const uint64_t* __restrict__ v, int64_t n, unsigned lo
     }
 }
 
+// a * b, or 2^64 - 1 when the product does not fit: with sat_add this gives
+// min(exact value, 2^64 - 1) for any sum of products of non-negative integers
+__device__ inline uint64_t sat_mul(uint64_t a, uint64_t b) {
+    return __umul64hi(a, b) ? ~0ull : a * b;
+}
+
 // Workload DP (Section V-C) for one tree edge (u_p -> u): the value of each
 // candidate of u_p is multiplied by the sum of the values of its list in C(u).
+// Exact unsigned 64-bit integers, saturating at 2^64 - 1.
 __global__ void k_workload_step(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int64_t np,
-                                const double* __restrict__ cu, double* __restrict__ cp) {
+                                const uint64_t* __restrict__ cu, uint64_t* __restrict__ cp) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
-        double sum = 0.0;
-        for (int64_t j = off[i]; j < off[i + 1]; ++j) sum += cu[adj[j]];
-        cp[i] *= sum;
+        uint64_t sum = 0;
+        for (int64_t j = off[i]; j < off[i + 1]; ++j) sum = sat_add(sum, cu[adj[j]]);
+        cp[i] = sat_mul(cp[i], sum);
     }
 }
 
-__global__ void k_fill_ones(double* __restrict__ x, int64_t n) {
+__global__ void k_fill_ones(uint64_t* __restrict__ x, int64_t n) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 1.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 1;
 }
 
 constexpr int kWaveBlock = 256;
@@ -800,18 +807,23 @@ extern "C" cstm_status cstm_cst_candidates(const cstm_cst* c, int32_t u, int32_t
 // W_CST = sum over root candidates of c_root, where c_u(v) is the product over
 // u's tree children u' of the sum of c_u'(v') over v's list in C(u') (1 at the
 // leaves): the number of tree-shaped paths the CST holds, an upper bound on
-// the embeddings below each candidate (Section V-C).  In double precision,
-// exact while the values stay below 2^53.
-double cstm_cst_workload_run(cstm_cst* c) {
-    if (c->workload >= 0) return c->workload;
-    if (c->empty) return c->workload = 0.0;
+// the embeddings below each candidate (Section V-C).  Unsigned 64-bit integer
+// arithmetic that saturates at 2^64 - 1, so every value is
+// min(exact value, 2^64 - 1).
+uint64_t cstm_cst_workload_run(cstm_cst* c) {
+    if (c->has_workload) return c->workload;
+    if (c->empty) {
+        c->root_w.clear();
+        c->has_workload = true;
+        return c->workload = 0;
+    }
     hipStream_t s = c->stream;
     DevArena mem;
     mem.ctx = c->ctx;
-    double* val[CSTM_MAX_K] = {};
+    uint64_t* val[CSTM_MAX_K] = {};
     for (int u = 0; u < c->k; ++u) {
         const int64_t n = c->ncand[u];
-        val[u] = mem.get_n<double>(n ? n : 1);
+        val[u] = mem.get_n<uint64_t>(n ? n : 1);
         if (n) {
             k_fill_ones<<<cstm_blocks(n, 256, 4096), 256, 0, s>>>(val[u], n);
             HIP_TRY(hipGetLastError());
@@ -825,16 +837,17 @@ double cstm_cst_workload_run(cstm_cst* c) {
         HIP_TRY(hipGetLastError());
     }
     const int64_t nr = c->ncand[c->root];
-    std::vector<double> h((size_t)nr);
-    if (nr) HIP_TRY(hipMemcpyAsync(h.data(), val[c->root], (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<uint64_t> h((size_t)nr);
+    if (nr) HIP_TRY(hipMemcpyAsync(h.data(), val[c->root], (size_t)nr * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    double w = 0.0;
-    for (double x : h) w += x;  // in candidate order: the same result every time
+    uint64_t w = 0;
+    for (uint64_t x : h) w = (w + x < w) ? ~0ull : w + x;
     c->root_w = std::move(h);
+    c->has_workload = true;
     return c->workload = w;
 }
 
-extern "C" cstm_status cstm_cst_workload(cstm_cst* c, double* w_out) {
+extern "C" cstm_status cstm_cst_workload(cstm_cst* c, uint64_t* w_out) {
     return cstm_guard([&] {
         CSTM_REQUIRE(c && w_out, CSTM_EINVAL, "NULL argument");
         HIP_TRY(hipSetDevice(c->ctx->device));

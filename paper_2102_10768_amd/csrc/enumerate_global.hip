@@ -42,8 +42,13 @@ struct GQueue {
     GLine head;         // next ticket a consumer takes (may run ahead of tail: waiting consumers)
     GLine tail;         // next ticket a producer fills
     GLine outstanding;  // tasks pushed and not finished
-    GLine abort;        // 1: give up (idle limit), 2: deadline passed
+    GLine abort;        // first reason to stop wins: 1 no progress for idle_limit, 2 deadline passed
+    GLine beat;         // s_memrealtime tick at which some busy wavefront last reported progress
 };
+
+// How often (s_memrealtime ticks, 100 MHz) a busy wavefront refreshes the
+// progress beat: 1 ms keeps the stores to that line rare.
+constexpr uint64_t kBeatTicks = 100000;
 
 struct GArgs {
     const CstDev* descs;  // nq descriptors, contiguous
@@ -61,7 +66,7 @@ struct GArgs {
     uint64_t cap;
     unsigned long long* row_cursor;
     unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks, summed] or nullptr
-    uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave may wait
+    uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave waits while no wave makes progress
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
     int donate_period;          // longest interval in chunks between donation checks (<= 0: never donate)
     int donate_min;             // shortest such interval
@@ -210,12 +215,16 @@ __device__ long long pop_task(const GArgs& A, int lane) {
                 }
                 const uint64_t now = now_ticks();
                 if (A.deadline && now > A.deadline) {
-                    atomicExch(&A.qu->abort.v, 2ull);
+                    atomicCAS(&A.qu->abort.v, 0ull, 2ull);
                     slot = -2;
                     break;
                 }
-                if (now - t0 > A.idle_limit) {
-                    atomicExch(&A.qu->abort.v, 1ull);
+                // give up only when nothing has progressed for the idle limit:
+                // neither this wait nor any busy wavefront's beat is that recent
+                const uint64_t beat = ld_rlx(&A.qu->beat.v);
+                const uint64_t last = beat > t0 ? beat : t0;
+                if (now > last && now - last > A.idle_limit) {
+                    atomicCAS(&A.qu->abort.v, 0ull, 1ull);
                     slot = -2;
                     break;
                 }
@@ -387,6 +396,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     const CstDev* D = nullptr;
     uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
+    uint64_t my_beat = 0;  // lane 0: when this wavefront last refreshed the progress beat
     // chunks between checks for waiting consumers, adapted per wavefront
     const uint32_t max_period = (uint32_t)(A.donate_period > 0 ? A.donate_period : 64);
     const uint32_t min_period = (uint32_t)A.donate_min < max_period ? (uint32_t)A.donate_min : max_period;
@@ -540,9 +550,15 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                     const unsigned long long lim = A.limits ? A.limits[q] : 0ull;
                     const bool publish = lim && cnt;
                     if (lane == 0) {
+                        const uint64_t now = now_ticks();
+                        if (now - my_beat > kBeatTicks) {
+                            __hip_atomic_store(&A.qu->beat.v, (unsigned long long)now, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            my_beat = now;
+                        }
                         if (ld_rlx(&A.qu->abort.v)) want = -1;
-                        else if (A.deadline && now_ticks() > A.deadline) {
-                            atomicExch(&A.qu->abort.v, 2ull);
+                        else if (A.deadline && now > A.deadline) {
+                            atomicCAS(&A.qu->abort.v, 0ull, 2ull);
                             want = -1;
                         } else if (lim && ld_rlx(&A.qstop[q])) {
                             want = -2;
@@ -670,7 +686,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     std::vector<int32_t> perm(nq);
     for (int q = 0; q < nq; ++q) perm[q] = q;
     if (nq > 1 && ctx->tune.batch_order > 0) {
-        std::vector<double> w(nq);
+        std::vector<uint64_t> w(nq);
         for (int q = 0; q < nq; ++q) w[q] = cstm_cst_workload_run(csts[q]);
         std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
     }
@@ -785,7 +801,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.cap = cap;
     A.row_cursor = row_cursor;
     A.stats = ctx->tune.collect_stats ? work : nullptr;
-    A.idle_limit = 100ull * 1000 * 1000 * 30;  // 30 s at 100 MHz
+    A.idle_limit = 100ull * 1000 * (uint64_t)ctx->tune.hbm_idle_ms;  // at 100 MHz
     A.deadline = o.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)o.deadline_ms : 0;
     int64_t longest = 0;
     for (int q = 0; q < nq; ++q) longest = std::max<int64_t>(longest, csts[q]->d_cst);
@@ -833,5 +849,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         ctx->last_enum = *st;  // kept even when the launch is reported as failed below
     }
     CSTM_REQUIRE(fin.abort.v != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
-    CSTM_REQUIRE(!fin.abort.v && fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
+    CSTM_REQUIRE(fin.abort.v != 1, CSTM_EDEVICE,
+                 "enumeration stopped: no wavefront made progress for " + std::to_string(ctx->tune.hbm_idle_ms) + " ms");
+    CSTM_REQUIRE(fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
 }

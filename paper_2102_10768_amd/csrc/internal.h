@@ -270,8 +270,9 @@ struct cstm_cst {
     uint64_t max_blob = 0;
     bool empty = false;  // some candidate set is empty: no embedding
     double t_build = 0, t_part = 0, t_enum = 0;
-    double workload = -1;  // W_CST of the workload DP (Section V-C), computed on first use
-    std::vector<double> root_w;  // c_root(v) for every root candidate, with workload
+    bool has_workload = false;     // W_CST computed (on first use)
+    uint64_t workload = 0;         // W_CST of the workload DP (Section V-C), saturating at 2^64 - 1
+    std::vector<uint64_t> root_w;  // c_root(v) for every root candidate, with workload
 };
 
 // ---------------------------------------------------------------- helpers shared across files
@@ -288,7 +289,7 @@ inline unsigned cstm_blocks(int64_t items, int per_block, unsigned cap = 1u << 2
 }
 
 // W_CST of the workload DP (Section V-C), cached in the CST.
-double cstm_cst_workload_run(cstm_cst* c);
+uint64_t cstm_cst_workload_run(cstm_cst* c);
 
 // Returns false (and leaves the CST unpartitioned) if the images would exceed max_total_bytes (0 = no limit).
 bool cstm_partition_run(cstm_cst* cst, uint64_t budget, int32_t max_list, uint64_t max_total_bytes = 0);

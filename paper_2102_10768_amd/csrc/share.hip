@@ -133,19 +133,23 @@ extern "C" cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_
         st.host_threads = host_threads;
         if (cst->empty) return;
         cstm_cst_workload_run(cst);
-        const std::vector<double>& w = cst->root_w;
+        const std::vector<uint64_t>& w = cst->root_w;
         const int64_t nr = (int64_t)w.size();
         if (nr == 0) return;
         const int64_t runs = std::min<int64_t>(nr, n_runs > 0 ? n_runs : 1024);
-        // Algorithm 3 over the runs, in root order
+        // Algorithm 3 over the runs, in root order.  Weights are exact
+        // integers (each c_root saturates at 2^64 - 1); the running sums are
+        // 128-bit, and only the comparison with delta times the total is
+        // taken in long double (64-bit significand).
         std::vector<int64_t> dev_ranges, host_ranges;
-        double wc = 0.0, wf = 0.0;
+        unsigned __int128 wc = 0, wf = 0;
         for (int64_t i = 0; i < runs; ++i) {
             const int64_t lo = i * nr / runs, hi = (i + 1) * nr / runs;
-            double wr = 0.0;
+            unsigned __int128 wr = 0;
             for (int64_t r = lo; r < hi; ++r) wr += w[(size_t)r];
-            std::vector<int64_t>& dst = (wc + wr < delta * (wc + wf + wr)) ? host_ranges : dev_ranges;
-            if (&dst == &host_ranges) {
+            const bool to_host = (long double)(wc + wr) < (long double)delta * (long double)(wc + wf + wr);
+            std::vector<int64_t>& dst = to_host ? host_ranges : dev_ranges;
+            if (to_host) {
                 wc += wr;
                 ++st.groups_host;
             } else {
@@ -158,8 +162,9 @@ extern "C" cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_
                 dst.push_back(hi);
             }
         }
-        st.w_host = wc;
-        st.w_device = wf;
+        const unsigned __int128 u64max = ~(uint64_t)0;
+        st.w_host = (uint64_t)(wc > u64max ? u64max : wc);
+        st.w_device = (uint64_t)(wf > u64max ? u64max : wf);
         const auto t0 = std::chrono::steady_clock::now();
         // the GPU's runs, launched from a thread of their own so that the host
         // search overlaps them

@@ -45,6 +45,7 @@ class cstm_tune(ctypes.Structure):
         ("last_level_sum", ctypes.c_int32),
         ("hbm_donate_min", ctypes.c_int32),
         ("batch_order", ctypes.c_int32),
+        ("hbm_idle_ms", ctypes.c_int32),
     ]
 
 
@@ -69,8 +70,8 @@ class cstm_enum_stats(ctypes.Structure):
 class cstm_share_stats(ctypes.Structure):
     _fields_ = [
         ("delta", ctypes.c_double),
-        ("w_host", ctypes.c_double),
-        ("w_device", ctypes.c_double),
+        ("w_host", ctypes.c_uint64),
+        ("w_device", ctypes.c_uint64),
         ("groups_host", ctypes.c_int64),
         ("groups_device", ctypes.c_int64),
         ("count_host", ctypes.c_uint64),
@@ -190,7 +191,7 @@ def load_library():
         "cstm_server_wait": (st, [P, U64, ctypes.c_double, ctypes.POINTER(cstm_request_result)]),
         "cstm_server_get_stats": (st, [P, ctypes.POINTER(cstm_server_stats)]),
         "cstm_server_destroy": (None, [P]),
-        "cstm_cst_workload": (st, [P, ctypes.POINTER(ctypes.c_double)]),
+        "cstm_cst_workload": (st, [P, ctypes.POINTER(ctypes.c_uint64)]),
         "cstm_cst_build_ordered": (st, [P, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]),
         "cstm_enumerate_shared": (st, [P, ctypes.c_double, I64, I32, ctypes.POINTER(U64),
                                        ctypes.POINTER(cstm_share_stats), P]),
@@ -389,9 +390,9 @@ class CST:
                                                  int(max_total_bytes), ctypes.byref(n)))
         return n.value
 
-    def workload(self) -> float:
-        """W_CST of the workload DP (Section V-C)."""
-        w = ctypes.c_double()
+    def workload(self) -> int:
+        """W_CST of the workload DP (Section V-C), exactly min(W_CST, 2^64 - 1)."""
+        w = ctypes.c_uint64()
         _check(load_library().cstm_cst_workload(self.handle, ctypes.byref(w)))
         return w.value
 

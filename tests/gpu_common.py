@@ -25,13 +25,18 @@ def ctx(mode: str = "auto"):
 
 def gpu_graph(g, mode: str = "auto"):
     """Load a synth.Graph through the device-pointer path (torch tensors)."""
+    return gpu_graph_in(ctx(mode), g)
+
+
+def gpu_graph_in(context, g):
+    """Load a synth.Graph into the given context (torch tensors, borrowed)."""
     import torch
     from paper_2102_10768_amd import cstm
 
     rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).cuda()
     col = torch.from_numpy(np.ascontiguousarray(g.col) if g.col.size else np.zeros(0, np.int32)).cuda()
     lab = torch.from_numpy(np.ascontiguousarray(g.label)).cuda()
-    return cstm.Graph(ctx(mode), rp, col, lab)
+    return cstm.Graph(context, rp, col, lab)
 
 
 def gpu_count(G, q, budget: int = 0, max_list: int = 0, partition: bool = True):

@@ -243,7 +243,7 @@ def test_workload_estimate_matches_reference_dp():
         _, w_ref = cst_ref.workload(ref)
         c = cstm.CST(ctx(), G, q.qlabel, q.qedges)
         w = c.workload()
-        assert w == float(w_ref)
+        assert w == cst_ref.saturate_u64(w_ref)
         n = c.count()
         c.close()
         assert w >= n
@@ -255,8 +255,49 @@ def test_workload_estimate_matches_reference_dp():
     qf = cf.query(fx["query"]["qlabel"], [tuple(e) for e in fx["query"]["qedges"]])
     ref = cst_ref.build_cst(gf, qf.qlabel, qf.qedges)
     c = cstm.CST(ctx(), gpu_graph(gf), qf.qlabel, qf.qedges)
-    assert c.workload() == float(cst_ref.workload(ref)[1])
+    assert c.workload() == cst_ref.workload(ref)[1] == 7
     c.close()
+
+
+def test_workload_is_exact_beyond_double_precision_and_saturates():
+    """W_CST of a star K_{1,s} (one label) in K_n is n (n-1)^s (root = centre):
+    K_{1,6} in K_300 is 300 * 299^6 ~ 2.1e17 > 2^53, held exactly; K_{1,8} in
+    K_400 is ~2.6e23 > 2^64 - 1, held as 2^64 - 1.  The reference DP
+    (Python integers) agrees on the first."""
+    from paper_2102_10768_amd import cstm
+
+    for n, s_ in ((300, 6), (400, 8)):
+        g = cf.complete(n)
+        q = cf.star_query(s_)
+        c = cstm.CST(ctx(), gpu_graph(g), q.qlabel, q.qedges)
+        want = n * (n - 1) ** s_
+        assert c.info()["root"] == 0
+        assert c.workload() == cst_ref.saturate_u64(want)
+        c.close()
+        if n == 300:
+            assert cst_ref.workload(cst_ref.build_cst(g, q.qlabel, q.qedges))[1] == want
+    assert 300 * 299 ** 6 > 2 ** 53 and 400 * 399 ** 8 > 2 ** 64
+
+
+def test_fig4_partition_counts_and_image_bytes_by_hand():
+    """Algorithm 2 on the fixture graph under the path order u0, u1, u3, u2
+    (Section V-B), values summed by hand: the full image is 352 B; at a
+    320-byte budget the root splits into {v1} (320 B) and {v2} (304 B); at
+    304 B {v1} splits again at u1 into two 288-byte images."""
+    from paper_2102_10768_amd import cstm
+
+    fx = json.load(open(os.path.join(GOLDEN, "fig4_fixture.json")))
+    gf = cf.graph_from_edges(fx["n"], [tuple(e) for e in fx["edges"]], fx["labels"])
+    qf = cf.query(fx["query"]["qlabel"], [tuple(e) for e in fx["query"]["qedges"]])
+    G = gpu_graph(gf, "lds")
+    for budget, sizes in ((1024, [352]), (320, [320, 304]), (304, [288, 288, 304])):
+        c = cstm.CST(ctx("lds"), G, qf.qlabel, qf.qedges)
+        assert c.info()["order"][:4] == [0, 1, 3, 2]
+        assert c.partition(budget) == len(sizes)
+        info = c.info()
+        assert info["part_bytes"] == sum(sizes) and info["max_part_bytes"] == max(sizes)
+        assert c.count() == 3
+        c.close()
 
 
 def test_batch_seeding_order_does_not_change_counts():

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from synth import Query, make_graph
-from gpu_common import ctx, gpu_graph
+from gpu_common import ctx, gpu_graph, gpu_graph_in
 
 pytestmark = pytest.mark.gpu
 
@@ -192,6 +192,35 @@ def test_last_level_sum_changes_no_count():
             assert abs(st_on["extensions"] - st_off["extensions"]) <= 0.01 * st_off["extensions"]
     finally:
         c.tune = {"last_level_sum": 1}
+
+
+def test_idle_wavefronts_keep_waiting_while_a_lone_search_progresses():
+    """With donation off, one wavefront runs the whole search of a query with a
+    single root candidate while every other wavefront waits for a task.  The
+    waiting ones must not give up while the busy one makes progress: the
+    launch runs far longer than the idle limit (20 ms here) and still returns
+    the exact count.  K_60 with one vertex of label 1: a 5-clique whose first
+    vertex has label 1 has 59*58*57*56 embeddings."""
+    import closed_forms as cf
+    from paper_2102_10768_amd import cstm
+
+    labels = [1] + [0] * 59
+    g = cf.complete(60, labels)
+    q = cf.clique_query([1, 0, 0, 0, 0])
+    c = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 1, "hbm_donate_period": -1,
+                              "hbm_idle_ms": 20})
+    G = gpu_graph_in(c, g)
+    cs = cstm.CST(c, G, q.qlabel, q.qedges)
+    assert cs.info()["cand"][0] == 1
+    n = cs.count()
+    st = c.last_enum_stats()
+    say(f"lone search: {n} embeddings in {st['kernel_ms']:.1f} ms, {st['image_bytes']} donations")
+    assert n == 59 * 58 * 57 * 56
+    assert st["image_bytes"] == 0  # nothing was donated
+    assert st["kernel_ms"] > 100.0  # the idle limit passed several times over
+    cs.close()
+    G.close()
+    c.close()
 
 
 def test_deadline_stops_an_on_chip_launch():
