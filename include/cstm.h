@@ -292,6 +292,26 @@ cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* row
 cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, const uint64_t* limits,
                                  uint64_t* counts_out, void* stream);
 
+/* Count the embeddings of one CST without allocating device memory: for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It runs the HBM-resident kernel of
+ * cstm_enumerate (whatever the context's enum_mode) with its task ring, queue
+ * state, descriptor copy and count in a fixed array of
+ * CSTM_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends; the ring has 2^16 task slots (cstm_enumerate's
+ * has 2^20).  It calls no allocator, no hipMalloc and no hipFree; the CST
+ * must already be built.  limit and deadline_s as for cstm_enumerate;
+ * *count_out receives the exact count, or min(total, limit).  Errors:
+ * CSTM_EINVAL for NULL arguments or a launch needing more scratch than the
+ * array holds; CSTM_ETIMEOUT / CSTM_EDEVICE as for cstm_enumerate.  Calls on
+ * one device share the array (it keeps the last call's contents; each call
+ * clears what must start at zero): the library serialises them with a lock
+ * held until the count is back, so they never overlap within a process,
+ * while a second process on the same device has its own copy. */
+#define CSTM_NOALLOC_SCRATCH_BYTES (12u << 20)
+cstm_status cstm_enumerate_noalloc(cstm_cst* cst, uint64_t limit, uint64_t* count_out, double deadline_s,
+                                   void* stream);
+
 /* ---------------------------------------------------------------- host share
  * Algorithm 3 (Section V-C): the root candidates of the CST are cut into
  * n_runs runs of consecutive candidates (0 = min(1024, #roots)), each weighed

@@ -225,6 +225,12 @@ extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_fre
         c->lds_per_wg = (int64_t)prop.sharedMemPerBlock;
         if (tune) c->tune = *tune;
         apply_defaults(c);
+        try {
+            cstm_noalloc_init(device);  // this device's address of the no-allocation scratch array
+        } catch (...) {
+            delete c;
+            throw;
+        }
         *out = c;
     });
 }

@@ -19,6 +19,8 @@
 // stored as ascending data-vertex ids, by binary search.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -672,6 +674,23 @@ __global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t
     }
 }
 
+// Clear n 32-bit words (a kernel rather than a memset node, so the same code
+// serves callers that capture the stream).
+__global__ void k_zero_words(uint32_t* __restrict__ p, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+void zero_words(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    if (!n) return;
+    k_zero_words<<<cstm_blocks((int64_t)n, 256, 2048), 256, 0, s>>>((uint32_t*)p, n);
+    HIP_TRY(hipGetLastError());
+}
+
+// Task-ring size of launches in a caller's fixed workspace: 2^16 slots.
+constexpr int kFixedQlog = 16;
+
 }  // namespace
 
 // Count (or list) the embeddings of nq CSTs in one launch, the CSTs read from
@@ -679,7 +698,8 @@ __global__ void k_seed(GArgs A, const int64_t* __restrict__ first, const int64_t
 void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                                uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
                                const EnumOpts& o, cstm_enum_stats* st, hipStream_t s) {
-    const int qlog = 20;
+    const bool fixed = o.fixed_ws != nullptr;
+    const int qlog = fixed ? kFixedQlog : 20;
     const unsigned long long qcap = 1ull << qlog;
     // seeding order: as given, or (batch_order > 0) the heaviest queries
     // (largest W_CST, Section V-C) first, so the long searches start early
@@ -746,9 +766,20 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     struct WsHold {
         cstm_ctx* ctx;
         void* p;
-        ~WsHold() { ctx->ws_release(p); }
-    } hold{ctx, ctx->ws_acquire(need)};
-    uint8_t* ws = (uint8_t*)hold.p;
+        ~WsHold() {
+            if (p) ctx->ws_release(p);
+        }
+    } hold{ctx, nullptr};
+    uint8_t* ws = nullptr;
+    if (fixed) {
+        CSTM_REQUIRE(need <= o.fixed_ws_bytes, CSTM_EINVAL,
+                     "launch needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                         std::to_string(o.fixed_ws_bytes) + " available");
+        ws = (uint8_t*)o.fixed_ws;
+    } else {
+        hold.p = ctx->ws_acquire(need);
+        ws = (uint8_t*)hold.p;
+    }
     GTask* tasks = (GTask*)ws;
     unsigned int* ready = (unsigned int*)(ws + off_ready);
     GQueue* qu = (GQueue*)(ws + off_qu);
@@ -768,12 +799,12 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         }
     if (any_limit) {
         HIP_TRY(hipMemcpyAsync(dlim, lim.data(), (size_t)nq * 8, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemsetAsync(dstop, 0, (size_t)nq * 4, s));
+        zero_words(dstop, (size_t)nq * 4, s);
     }
     for (int q = 0; q < nq; ++q)
         HIP_TRY(hipMemcpyAsync(descs + q, &csts[q]->host_desc, sizeof(CstDev), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ready, 0, ready_b, s));
-    HIP_TRY(hipMemsetAsync(work, 0, 8 * sizeof(unsigned long long), s));
+    zero_words(ready, ready_b, s);
+    zero_words(work, 8 * sizeof(unsigned long long), s);
     GQueue init;
     std::memset(&init, 0, sizeof(init));
     init.tail.v = total;
@@ -794,7 +825,8 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     A.ready = ready;
     A.qmask = qcap - 1;
     A.qlog = qlog;
-    A.margin = 1ull << 15;
+    // room kept free in the ring for pushes already decided (far more than the waves in flight)
+    A.margin = fixed ? qcap / 4 : 1ull << 15;
     A.counts = counts_dev;
     A.list = list;
     A.rows = rows;
@@ -816,19 +848,24 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + ns + 1, meta + 2 * ns + 1,
                                                                   meta + 3 * ns + 1, dsegq, ns, total);
     HIP_TRY(hipGetLastError());
-    hipEvent_t ev[2];
-    HIP_TRY(hipEventCreate(&ev[0]));
-    HIP_TRY(hipEventCreate(&ev[1]));
-    HIP_TRY(hipEventRecord(ev[0], s));
     const unsigned grid = (unsigned)(ctx->num_cus * ctx->tune.hbm_wgs_per_cu);
-    k_enumerate_global<<<grid, 256, 0, s>>>(A);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(hipEventSynchronize(ev[1]));
     float kernel_ms = 0;
-    HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    if (fixed) {
+        k_enumerate_global<<<grid, 256, 0, s>>>(A);
+        HIP_TRY(hipGetLastError());
+    } else {
+        hipEvent_t ev[2];
+        HIP_TRY(hipEventCreate(&ev[0]));
+        HIP_TRY(hipEventCreate(&ev[1]));
+        HIP_TRY(hipEventRecord(ev[0], s));
+        k_enumerate_global<<<grid, 256, 0, s>>>(A);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(hipEventSynchronize(ev[1]));
+        HIP_TRY(hipEventElapsedTime(&kernel_ms, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
     unsigned long long h[8];
     GQueue fin{};
     HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -852,4 +889,68 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     CSTM_REQUIRE(fin.abort.v != 1, CSTM_EDEVICE,
                  "enumeration stopped: no wavefront made progress for " + std::to_string(ctx->tune.hbm_idle_ms) + " ms");
     CSTM_REQUIRE(fin.outstanding.v == 0, CSTM_EDEVICE, "enumeration work queue did not drain");
+}
+
+// ---------------------------------------------------------------- no-allocation entry point
+//
+// The task ring, queue state, descriptors and counts of cstm_enumerate_noalloc
+// live in one file-scope device array.  In host code `scratch` names a host
+// stand-in, not device memory: every host use goes through the address
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[CSTM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                // guards g_scratch_ptr
+void* g_scratch_ptr[kMaxDevices] = {};  // this device's copy of `scratch`
+std::mutex g_call_mu[kMaxDevices];      // one no-allocation call at a time per device
+}  // namespace
+
+void cstm_noalloc_init(int device) {
+    CSTM_REQUIRE(device >= 0 && device < kMaxDevices, CSTM_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CSTM_REQUIRE(p != nullptr, CSTM_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[device] = p;
+}
+
+extern "C" cstm_status cstm_enumerate_noalloc(cstm_cst* cst, uint64_t limit, uint64_t* count_out, double deadline_s,
+                                              void* stream) {
+    uint64_t count = 0;
+    cstm_status status = cstm_guard([&] {
+        CSTM_REQUIRE(cst && count_out, CSTM_EINVAL, "NULL argument");
+        CSTM_REQUIRE(deadline_s == deadline_s, CSTM_EINVAL, "deadline is NaN");
+        cstm_ctx* ctx = cst->ctx;
+        const int dev = ctx->device;
+        HIP_TRY(hipSetDevice(dev));
+        uint8_t* base = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            base = (uint8_t*)(dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr);
+        }
+        CSTM_REQUIRE(base, CSTM_EDEVICE, "scratch array not set up on this device");
+        if (cst->empty) return;
+        hipStream_t s = stream ? (hipStream_t)stream : cst->stream;
+        std::lock_guard<std::mutex> call(g_call_mu[dev]);
+        // [0, 256): the count and the (unused) row cursor; the rest: the launch workspace
+        unsigned long long* counts = (unsigned long long*)base;
+        zero_words(counts, 2 * sizeof(unsigned long long), s);
+        EnumOpts o;
+        o.limits = limit ? &limit : nullptr;
+        o.deadline_ms = deadline_s > 0 ? (int64_t)(deadline_s * 1e3) + 1 : ctx->tune.deadline_ms;
+        o.fixed_ws = base + 256;
+        o.fixed_ws_bytes = CSTM_NOALLOC_SCRATCH_BYTES - 256;
+        cstm_cst* one[1] = {cst};
+        const int slot0 = 0;
+        cstm_enum_stats st{};
+        cstm_enumerate_global_run(ctx, 1, one, &slot0, 0, nullptr, 0, counts, counts + 1, o, &st, s);
+        unsigned long long h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, counts, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        count = (limit && h > limit) ? limit : (uint64_t)h;
+    });
+    if (count_out) *count_out = count;
+    return status;
 }

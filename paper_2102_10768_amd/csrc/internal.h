@@ -301,7 +301,15 @@ struct EnumOpts {
     // [lo, hi) index pairs (nullptr: all of them); forces the HBM-resident kernel
     const int64_t* root_ranges = nullptr;
     int64_t n_ranges = 0;
+    // HBM-resident kernel only: run in this caller-provided workspace (a
+    // smaller task ring, no allocation and no timing events) instead of one
+    // lent by the context
+    void* fixed_ws = nullptr;
+    size_t fixed_ws_bytes = 0;
 };
+// Look up this device's copy of the no-allocation scratch array (once per
+// device, with the device current); cstm_ctx_create calls it.
+void cstm_noalloc_init(int device);
 void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                             uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
                             const EnumOpts& o, cstm_enum_stats* st, hipStream_t s);

@@ -143,7 +143,11 @@ EXPORTS = [
     "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
     "cstm_server_create", "cstm_server_submit", "cstm_server_poll", "cstm_server_wait", "cstm_server_get_stats",
     "cstm_server_destroy", "cstm_cst_workload", "cstm_cst_build_ordered", "cstm_enumerate_shared",
+    "cstm_enumerate_noalloc",
 ]
+
+# bytes of the fixed device array cstm_enumerate_noalloc works in (CSTM_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 12 << 20
 
 _lib = None
 
@@ -195,6 +199,7 @@ def load_library():
         "cstm_cst_build_ordered": (st, [P, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]),
         "cstm_enumerate_shared": (st, [P, ctypes.c_double, I64, I32, ctypes.POINTER(U64),
                                        ctypes.POINTER(cstm_share_stats), P]),
+        "cstm_enumerate_noalloc": (st, [P, U64, ctypes.POINTER(U64), ctypes.c_double, P]),
         "cstm_last_error": (ctypes.c_char_p, []),
         "cstm_version": (ctypes.c_char_p, []),
     }
@@ -228,12 +233,25 @@ def _stream_ptr(stream):
 class Context:
     """A device context (``cstm_ctx_create``).  ``tune`` is a dict of cstm_tune fields."""
 
-    def __init__(self, device: int = 0, tune: dict | None = None, torch_allocator: bool = False):
+    def __init__(self, device: int = 0, tune: dict | None = None, torch_allocator: bool = False, allocator=None):
+        """``allocator``: optional (alloc(nbytes) -> device pointer or 0, free(ptr)) pair
+        of Python callables used for every device allocation of the library."""
         lib = load_library()
         self._keep = []
         alloc = ALLOC_FN()
         free = FREE_FN()
-        if torch_allocator:
+        if allocator is not None:
+            user_alloc, user_free = allocator
+
+            def _alloc_cb(nbytes, user):
+                return user_alloc(int(nbytes)) or None
+
+            def _free_cb(ptr, user):
+                user_free(ptr)
+
+            alloc, free = ALLOC_FN(_alloc_cb), FREE_FN(_free_cb)
+            self._keep += [alloc, free]
+        elif torch_allocator:
             import torch
 
             def _alloc(nbytes, user):
@@ -429,6 +447,13 @@ class CST:
         c, w = ctypes.c_uint64(), ctypes.c_uint64()
         _check(load_library().cstm_enumerate(self.handle, 0, int(limit), None, 0, ctypes.byref(c), ctypes.byref(w),
                                              float(deadline_s), _stream_ptr(stream)))
+        return c.value
+
+    def count_noalloc(self, stream=None, limit: int = 0, deadline_s: float = 0.0) -> int:
+        """As :meth:`count`, through ``cstm_enumerate_noalloc`` (no device allocation)."""
+        c = ctypes.c_uint64()
+        _check(load_library().cstm_enumerate_noalloc(self.handle, int(limit), ctypes.byref(c), float(deadline_s),
+                                                     _stream_ptr(stream)))
         return c.value
 
     def list(self, cap: int, stream=None, allow_overflow: bool = False, limit: int = 0, deadline_s: float = 0.0):
