@@ -1,6 +1,4 @@
-// context.hip -- context, device memory, error reporting and scan helpers.
-#include <hipcub/hipcub.hpp>
-
+// context.hip -- context, device memory and error reporting.
 #include <cstring>
 
 #include "internal.h"
@@ -82,21 +80,6 @@ void cstm_ctx::release_pool() {
     }
 }
 
-void* cstm_ctx::scratch(size_t bytes) {
-    if (bytes > tmp_bytes) {
-        if (tmp) {
-            (void)hipDeviceSynchronize();
-            dfree(tmp);
-        }
-        tmp = nullptr;
-        tmp_bytes = 0;
-        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 2;
-        tmp = dmalloc(want);
-        tmp_bytes = want;
-    }
-    return tmp;
-}
-
 void* cstm_ctx::ws_acquire(size_t bytes) {
     {
         std::lock_guard<std::mutex> lk(ws_mu);
@@ -138,40 +121,6 @@ void DevArena::clear() {
     if (!ctx) return;
     for (void* p : blocks) ctx->dfree(p);
     blocks.clear();
-}
-
-// ---------------------------------------------------------------- scans
-
-template <class T>
-static int64_t exclusive_scan_impl(cstm_ctx* ctx, const T* in, T* out, int64_t n, hipStream_t s) {
-    // out[0..n-1] = exclusive prefix sums, out[n] = total
-    if (n == 0) {
-        T zero = 0;
-        HIP_TRY(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return 0;
-    }
-    size_t tmp_bytes = 0;
-    std::lock_guard<std::mutex> lk(ctx->scratch_mu);
-    HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, out + 1, (int)n, s));
-    void* tmp = ctx->scratch(tmp_bytes);
-    HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out + 1, (int)n, s));
-    T zero = 0;
-    HIP_TRY(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
-    T total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, out + n, sizeof(T), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return (int64_t)total;
-}
-
-int64_t cstm_exclusive_scan_i64(cstm_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
-    CSTM_REQUIRE(n < (int64_t)1 << 31, CSTM_EINVAL, "scan length exceeds 2^31");
-    return exclusive_scan_impl<int64_t>(ctx, in, out, n, s);
-}
-
-int64_t cstm_exclusive_scan_i32(cstm_ctx* ctx, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
-    CSTM_REQUIRE(n < (int64_t)1 << 31, CSTM_EINVAL, "scan length exceeds 2^31");
-    return exclusive_scan_impl<int32_t>(ctx, in, out, n, s);
 }
 
 // ---------------------------------------------------------------- context API
@@ -239,7 +188,6 @@ extern "C" void cstm_ctx_destroy(cstm_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    ctx->dfree(ctx->tmp);
     for (void* p : ctx->ws_all) ctx->dfree(p);
     {
         std::lock_guard<std::mutex> lk(ctx->pool_mu);

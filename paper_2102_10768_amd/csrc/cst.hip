@@ -11,9 +11,15 @@
 //   4. the tree lists, the path-based matching order (Section V-B), and the
 //      non-tree candidate edges (stored once, from the earlier to the later
 //      endpoint in the order, which is the direction enumeration reads).
-// Membership of a data vertex w in C(u) is one range test on w's label-group
-// rank plus one lookup in a rank-indexed table, so every scan below is a
-// coalesced walk over CSR rows with one gather per neighbour.
+// Membership of a data vertex w in C(u) is one range test on w's packed
+// (label, rank) key plus one lookup in a rank-indexed table.  The rows of a
+// parent's candidates are walked once per tree edge, in the top-down pass:
+// each entry's rank test is kept (`erank`), and the bottom-up test and both
+// passes over the tree list read it back in order instead of gathering keys
+// again.  Sizes stay on the device (kernels read them from a small table and
+// run grids sized by host-side bounds from the label index), so a build waits
+// for the device four times: for the tree-list sizes, the path counts of the
+// order, the non-tree list sizes, and at the end.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -36,16 +42,17 @@ __device__ inline int mbcnt(uint64_t m) {
 
 // Rows of a candidate array laid end to end: entry t of the flattened space is
 // entry t - rowoff[i] of the CSR row of candidate i, where rowoff is the
-// exclusive prefix sum of the candidates' degrees.  Kernels walk this space in
-// tiles of kTile entries, one wavefront per tile, so a hub's long row is shared
-// by many wavefronts and short rows are packed together.
+// exclusive prefix sum of the candidates' degrees.  The number of candidates
+// lives on the device (*n), and rowoff[*n] is the number of entries.  Kernels
+// walk this space in tiles of kTile entries, one wavefront per tile, so a
+// hub's long row is shared by many wavefronts and short rows are packed
+// together.
 constexpr int kTile = 512;
 
 struct Rows {
     const int32_t* cand;    // candidate data-vertex ids
     const int64_t* rowoff;  // n + 1 prefix sums of their degrees
-    int64_t n;
-    int64_t total;          // rowoff[n]
+    const int64_t* n;       // device: number of candidates
 };
 
 // The candidate whose row holds flattened entry t: the last i in [lo, hi]
@@ -59,42 +66,63 @@ __device__ inline int64_t owner_of(const int64_t* __restrict__ rowoff, int64_t l
     return lo;
 }
 
-__global__ void k_cand_degrees(const int32_t* __restrict__ cand, int64_t n, const int64_t* __restrict__ row_ptr,
-                               int64_t* __restrict__ deg) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// Walk every tile of the flattened rows; body(t0, t1, lo, hi) with the
+// tile's entry range and the range of candidates owning it.
+template <class F>
+__device__ inline void for_tiles(const Rows& R, F&& body) {
+    const int64_t n = *R.n;
+    if (n <= 0) return;
+    const int64_t total = R.rowoff[n];
+    const int64_t ntiles = (total + kTile - 1) / kTile;
+    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
+        const int64_t t0 = tile * kTile, t1 = t0 + kTile < total ? t0 + kTile : total;
+        const int64_t lo = owner_of(R.rowoff, 0, n - 1, t0);
+        const int64_t hi = owner_of(R.rowoff, lo, n - 1, t1 - 1);
+        body(tile, t0, t1, lo, hi);
+    }
+}
+
+__global__ void k_cand_degrees(const int32_t* __restrict__ cand, const int64_t* __restrict__ n_dev,
+                               const int64_t* __restrict__ row_ptr, int64_t* __restrict__ deg) {
+    const int64_t n = *n_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int32_t v = cand[i];
         deg[i] = row_ptr[v + 1] - row_ptr[v];
     }
 }
 
-// Top-down marking: every neighbour of a parent candidate that passes u's
-// label/degree filter is marked in u's rank table.
+// Top-down marking for a tree edge (u_p -> u): every neighbour of a parent
+// candidate that passes u's label/degree filter is marked in u's rank table,
+// and each entry's rank (or -1) is kept in erank for the later passes.
+template <class K>
 __global__ void k_mark(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                       const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0, int32_t* __restrict__ mark) {
+                       const K* __restrict__ lkey, K base, int64_t cnt0, int32_t* __restrict__ mark,
+                       int32_t* __restrict__ erank) {
     const int lane = lane_id();
-    const int64_t ntiles = (R.total + kTile - 1) / kTile;
-    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
-        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
-        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
-        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
+    for_tiles(R, [&](int64_t, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
         for (int64_t t = t0 + lane; t < t1; t += CSTM_WAVE) {
             const int64_t i = owner_of(R.rowoff, lo, hi, t);
             const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
-            const uint64_t d = lab_rank[col[j]] - key;
-            if (d < (uint64_t)cnt0) mark[d] = 1;
+            const uint64_t d = (uint64_t)(K)(lkey[col[j]] - base);
+            const bool hit = d < (uint64_t)cnt0;
+            erank[t] = hit ? (int32_t)d : -1;
+            if (hit) mark[d] = 1;
         }
-    }
+    });
 }
 
-// marks -> candidate indices: C(u) in rank order (degree desc, id asc).
+// marks -> candidate indices: C(u) in rank order (degree desc, id asc); each
+// candidate's rank is kept in tdrank.
 __global__ void k_assign(int32_t* __restrict__ loc, const int32_t* __restrict__ scan, int64_t cnt0,
-                         const int32_t* __restrict__ perm_base, int32_t* __restrict__ cand) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+                         const int32_t* __restrict__ perm_base, int32_t* __restrict__ cand,
+                         int32_t* __restrict__ tdrank) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < cnt0; r += stride) {
         if (loc[r]) {
-            int32_t j = scan[r];
+            const int32_t j = scan[r];
             cand[j] = perm_base[r];
+            tdrank[j] = (int32_t)r;
             loc[r] = j;
         } else {
             loc[r] = -1;
@@ -103,17 +131,19 @@ __global__ void k_assign(int32_t* __restrict__ loc, const int32_t* __restrict__ 
 }
 
 __global__ void k_iota_root(int32_t* __restrict__ loc, int64_t cnt0, const int32_t* __restrict__ perm_base,
-                            int32_t* __restrict__ cand) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+                            int32_t* __restrict__ cand, int32_t* __restrict__ tdrank) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < cnt0; r += stride) {
         loc[r] = (int32_t)r;
         cand[r] = perm_base[r];
+        tdrank[r] = (int32_t)r;
     }
 }
 
+// One tree child of the vertex being refined: the ranks its top-down pass
+// kept over the vertex's rows, and its (already refined) rank table.
 struct ChildRef {
-    uint64_t key;
-    int64_t cnt0;
+    const int32_t* erank;
     const int32_t* loc;
 };
 struct ChildSet {
@@ -122,23 +152,22 @@ struct ChildSet {
 };
 
 // Bottom-up validity: a candidate needs a neighbour in every refined child set.
-__global__ void k_valid(const int32_t* __restrict__ cand, int64_t n, const int64_t* __restrict__ row_ptr,
-                        const int32_t* __restrict__ col, const uint64_t* __restrict__ lab_rank, ChildSet ch,
-                        int32_t* __restrict__ flag) {
+// One wavefront per candidate, reading the kept ranks of its row.
+__global__ void k_valid(Rows R, ChildSet ch, int32_t* __restrict__ flag) {
     const int lane = lane_id();
+    const int64_t n = *R.n;
     for (int64_t i = global_wave(); i < n; i += num_waves()) {
-        int32_t v = cand[i];
-        int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        const int64_t b = R.rowoff[i], e = R.rowoff[i + 1];
         bool ok = true;
         for (int c = 0; c < ch.n && ok; ++c) {
             const ChildRef cr = ch.c[c];
             bool found = false;
             for (int64_t j0 = b; j0 < e && !found; j0 += CSTM_WAVE) {
-                int64_t j = j0 + lane;
+                const int64_t j = j0 + lane;
                 bool hit = false;
                 if (j < e) {
-                    uint64_t d = lab_rank[col[j]] - cr.key;
-                    hit = d < (uint64_t)cr.cnt0 && cr.loc[d] >= 0;
+                    const int32_t r = cr.erank[j];
+                    hit = r >= 0 && cr.loc[r] >= 0;
                 }
                 found = ballot(hit) != 0;
             }
@@ -148,68 +177,154 @@ __global__ void k_valid(const int32_t* __restrict__ cand, int64_t n, const int64
     }
 }
 
-__global__ void k_refine(const int32_t* __restrict__ cand_old, const int32_t* __restrict__ flag,
-                         const int32_t* __restrict__ scan, int64_t n, const uint64_t* __restrict__ lab_rank,
-                         uint64_t key, int32_t* __restrict__ loc, int32_t* __restrict__ cand_new) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// Compaction of the top-down set to the refined one; newidx maps a top-down
+// index to the refined index (or -1), the rank table follows.
+__global__ void k_refine(const int32_t* __restrict__ cand_td, const int32_t* __restrict__ tdrank,
+                         const int32_t* __restrict__ flag, const int32_t* __restrict__ scan,
+                         const int64_t* __restrict__ n_dev, int32_t* __restrict__ loc, int32_t* __restrict__ cand,
+                         int32_t* __restrict__ newidx) {
+    const int64_t n = *n_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int32_t v = cand_old[i];
-        uint64_t r = lab_rank[v] - key;
         if (flag[i]) {
-            int32_t j = scan[i];
-            cand_new[j] = v;
-            loc[r] = j;
+            const int32_t j = scan[i];
+            cand[j] = cand_td[i];
+            loc[tdrank[i]] = j;
+            newidx[i] = j;
         } else {
-            loc[r] = -1;
+            loc[tdrank[i]] = -1;
+            newidx[i] = -1;
         }
     }
 }
 
-// List sizes: |N_G(v) ∩ C(u')| per candidate v of the list's owner, added to
-// cnt (zeroed by the caller) once per run of lanes with the same owner; the
-// number of list entries in each tile goes to tile_cnt.
-__global__ void k_list_count(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                             const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0,
+__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
+
+// Adds the hits of one 64-entry step to the per-owner counts: owners never
+// decrease across lanes, so one atomic per run of lanes with the same owner.
+__device__ inline void add_runs(int64_t owner, int32_t ni, uint64_t hits, unsigned long long* __restrict__ cnt) {
+    const int lane = lane_id();
+    const int64_t prev = __shfl_up(owner, 1, CSTM_WAVE);
+    const bool head = lane == 0 || prev != owner;
+    const uint64_t heads = ballot(head);
+    if (head && ni >= 0) {
+        const uint64_t later = lane == CSTM_WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+        const uint64_t upto = later ? (later & (~later + 1)) - 1 : ~0ull;  // bits below the next head
+        const uint64_t run = upto & ~((1ull << lane) - 1);
+        const int c = __popcll(hits & run);
+        if (c) atomicAdd(&cnt[ni], (unsigned long long)c);
+    }
+}
+
+// Tree list (u_p -> u) sizes from the kept ranks: an entry is in the list of
+// its (refined) owner when its rank survives in u's rank table.  Per refined
+// owner counts go to cnt (zeroed by the caller), per tile counts to tile_cnt.
+__global__ void k_tree_count(Rows R, const int32_t* __restrict__ newidx, const int32_t* __restrict__ erank,
                              const int32_t* __restrict__ loc, unsigned long long* __restrict__ cnt,
                              int64_t* __restrict__ tile_cnt) {
     const int lane = lane_id();
-    const int64_t ntiles = (R.total + kTile - 1) / kTile;
-    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
-        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
-        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
-        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
+    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
         int64_t in_tile = 0;
         for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
             const int64_t t = s0 + lane;
             const bool in = t < t1;
             const int64_t i = in ? owner_of(R.rowoff, lo, hi, t) : hi;
+            const int32_t ni = newidx ? newidx[i] : (int32_t)i;
             bool hit = false;
-            if (in) {
-                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
-                const uint64_t d = lab_rank[col[j]] - key;
-                hit = d < (uint64_t)cnt0 && loc[d] >= 0;
+            if (in && ni >= 0) {
+                const int32_t r = erank[t];
+                hit = r >= 0 && loc[r] >= 0;
             }
             const uint64_t hits = ballot(hit);
             in_tile += __popcll(hits);
-            // owners never decrease across lanes: one atomic per run of equal owners
-            const int64_t prev = __shfl_up(i, 1, CSTM_WAVE);
-            const bool head = lane == 0 || prev != i;
-            const uint64_t heads = ballot(head);
-            if (head) {
-                const uint64_t later = lane == CSTM_WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
-                const uint64_t upto = later ? (later & (~later + 1)) - 1 : ~0ull;  // bits below the next head
-                const uint64_t run = upto & ~((1ull << lane) - 1);
-                const int c = __popcll(hits & run);
-                if (c) atomicAdd(&cnt[i], (unsigned long long)c);
-            }
+            add_runs(i, ni, hits, cnt);
         }
         if (lane == 0) tile_cnt[tile] = in_tile;
-    }
+    });
+}
+
+// Tree list entries, in G's row order (ascending data-vertex id), as indices
+// into C(u): the hits of the flattened space are numbered in order, tile by
+// tile from tile_base, which lays the lists of consecutive owners end to end
+// exactly as the offsets from the per-owner counts do.
+__global__ void k_tree_fill(Rows R, const int32_t* __restrict__ newidx, const int32_t* __restrict__ erank,
+                            const int32_t* __restrict__ loc, const int64_t* __restrict__ tile_base,
+                            int32_t* __restrict__ adj) {
+    const int lane = lane_id();
+    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
+        int64_t out = tile_base[tile];
+        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
+            const int64_t t = s0 + lane;
+            int32_t idx = -1;
+            if (t < t1) {
+                const int64_t i = owner_of(R.rowoff, lo, hi, t);
+                const int32_t ni = newidx ? newidx[i] : (int32_t)i;
+                const int32_t r = erank[t];
+                if (ni >= 0 && r >= 0) idx = loc[r];
+            }
+            const uint64_t m = ballot(idx >= 0);
+            if (idx >= 0) adj[out + mbcnt(m)] = idx;
+            out += __popcll(m);
+        }
+    });
+}
+
+// Non-tree list (a -> b) sizes over a's rows: each entry's index in C(b) (or
+// -1) is kept in E for the fill, per refined owner counts go to cnt, per tile
+// counts to tile_cnt.
+template <class K>
+__global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const int64_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col, const K* __restrict__ lkey, K base, int64_t cnt0,
+                           const int32_t* __restrict__ loc, int32_t* __restrict__ E,
+                           unsigned long long* __restrict__ cnt, int64_t* __restrict__ tile_cnt) {
+    const int lane = lane_id();
+    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
+        int64_t in_tile = 0;
+        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
+            const int64_t t = s0 + lane;
+            const bool in = t < t1;
+            const int64_t i = in ? owner_of(R.rowoff, lo, hi, t) : hi;
+            const int32_t ni = newidx ? newidx[i] : (int32_t)i;
+            int32_t idx = -1;
+            if (in && ni >= 0) {
+                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
+                const uint64_t d = (uint64_t)(K)(lkey[col[j]] - base);
+                if (d < (uint64_t)cnt0) idx = loc[d];
+            }
+            if (in) E[t] = idx;
+            const uint64_t hits = ballot(idx >= 0);
+            in_tile += __popcll(hits);
+            add_runs(i, ni, hits, cnt);
+        }
+        if (lane == 0) tile_cnt[tile] = in_tile;
+    });
+}
+
+// Non-tree list entries from E, with their data-vertex ids (ascending within
+// each list, since rows are sorted).
+__global__ void k_nt_fill(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                          const int32_t* __restrict__ E, const int64_t* __restrict__ tile_base,
+                          int32_t* __restrict__ adj, int32_t* __restrict__ adj_gid) {
+    const int lane = lane_id();
+    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
+        int64_t out = tile_base[tile];
+        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
+            const int64_t t = s0 + lane;
+            const int32_t idx = t < t1 ? E[t] : -1;
+            const uint64_t m = ballot(idx >= 0);
+            if (idx >= 0) {
+                const int64_t i = owner_of(R.rowoff, lo, hi, t);
+                adj[out + mbcnt(m)] = idx;
+                adj_gid[out + mbcnt(m)] = col[row_ptr[R.cand[i]] + (t - R.rowoff[i])];
+            }
+            out += __popcll(m);
+        }
+    });
 }
 
 // Largest list length, from the list offsets.
 __global__ void k_max_len(const int64_t* __restrict__ off, int64_t n, int* __restrict__ max_len) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int m = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int64_t len = off[i + 1] - off[i];
@@ -222,40 +337,6 @@ __global__ void k_max_len(const int64_t* __restrict__ off, int64_t n, int* __res
     if (lane_id() == 0 && m) atomicMax(max_len, m);
 }
 
-// List entries, in G's row order (ascending data-vertex id), as indices into
-// C(u'): the hits of the flattened space are numbered in order, tile by tile
-// from tile_base, which lays the lists of consecutive owners end to end exactly
-// as the offsets from the per-owner counts do.
-__global__ void k_list_fill(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                            const uint64_t* __restrict__ lab_rank, uint64_t key, int64_t cnt0,
-                            const int32_t* __restrict__ loc, const int64_t* __restrict__ tile_base,
-                            int32_t* __restrict__ adj, int32_t* __restrict__ adj_gid) {
-    const int lane = lane_id();
-    const int64_t ntiles = (R.total + kTile - 1) / kTile;
-    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
-        const int64_t t0 = tile * kTile, t1 = t0 + kTile < R.total ? t0 + kTile : R.total;
-        const int64_t lo = owner_of(R.rowoff, 0, R.n - 1, t0);
-        const int64_t hi = owner_of(R.rowoff, lo, R.n - 1, t1 - 1);
-        int64_t out = tile_base[tile];
-        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
-            const int64_t t = s0 + lane;
-            int32_t idx = -1, w = 0;
-            if (t < t1) {
-                const int64_t i = owner_of(R.rowoff, lo, hi, t);
-                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
-                w = col[j];
-                const uint64_t d = lab_rank[w] - key;
-                if (d < (uint64_t)cnt0) idx = loc[d];
-            }
-            const uint64_t m = ballot(idx >= 0);
-            if (idx >= 0) {
-                adj[out + mbcnt(m)] = idx;
-                if (adj_gid) adj_gid[out + mbcnt(m)] = w;
-            }
-            out += __popcll(m);
-        }
-    }
-}
 
 __device__ inline uint64_t sat_add(uint64_t a, uint64_t b) {
     uint64_t s = a + b;
@@ -387,70 +468,25 @@ struct EventTimer {
     }
 };
 
-}  // namespace
-
-// Flattened rows of n candidates: degrees, then their prefix sums into rowoff
-// (n + 1 entries).  Returns the total number of row entries.
-static Rows flat_rows(cstm_cst* c, const int32_t* cand, int64_t n, int64_t* deg, int64_t* rowoff) {
-    hipStream_t s = c->stream;
-    if (n) {
-        k_cand_degrees<<<cstm_blocks(n, 256, 4096), 256, 0, s>>>(cand, n, c->g->row_ptr, deg);
-        HIP_TRY(hipGetLastError());
-    }
-    Rows R;
-    R.cand = cand;
-    R.rowoff = rowoff;
-    R.n = n;
-    R.total = cstm_exclusive_scan_i64(c->ctx, deg, rowoff, n, s);
-    return R;
-}
-
-static unsigned tile_grid(int64_t total) {
-    const int64_t tiles = (total + kTile - 1) / kTile;
+// Grid of a tile walk over at most `bound` row entries (one wavefront per tile).
+unsigned tile_grid(int64_t bound) {
+    const int64_t tiles = (bound + kTile - 1) / kTile;
     return wave_grid(tiles > 0 ? tiles : 1);
 }
 
-// The lists of `from` (a query vertex) into `to`, using to's rank table.
-// Scratch: deg, rowoff and cnt hold at least #C(from) + 1 int64 entries.
-// The longest list goes to the device int *d_max (zeroed by the caller), read
-// back once after all lists; blocks the fill kernel still uses go to `later`,
-// released after the build's last wait.
-static void build_lists(cstm_cst* c, int from, int to, int32_t* const* loc, EdgeLists& el, int* d_max,
-                        int64_t* deg, int64_t* rowoff, int64_t* cnt, bool with_gid, std::vector<void*>& later) {
-    const cstm_graph* g = c->g;
-    hipStream_t s = c->stream;
-    const int64_t np = c->ncand[from];
-    uint64_t key = (uint64_t)c->qlabel[to] << 32;
-    el.off = c->mem.get_n<int64_t>(np + 1);
-    const Rows R = flat_rows(c, c->cand[from], np, deg, rowoff);
-    const int64_t ntiles = (R.total + kTile - 1) / kTile;
-    int64_t* tile_cnt = c->mem.get_n<int64_t>(ntiles + 1);
-    if (np) HIP_TRY(hipMemsetAsync(cnt, 0, (size_t)np * sizeof(int64_t), s));
-    if (ntiles) {
-        k_list_count<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank, key, c->cnt0[to],
-                                                               loc[to], (unsigned long long*)cnt, tile_cnt);
-        HIP_TRY(hipGetLastError());
-    }
-    el.entries = cstm_exclusive_scan_i64(c->ctx, cnt, el.off, np, s);
-    if (np) {
-        k_max_len<<<cstm_blocks(np, 256, 1024), 256, 0, s>>>(el.off, np, d_max);
-        HIP_TRY(hipGetLastError());
-    }
-    el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-    if (with_gid) el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-    if (ntiles && el.entries) {
-        int64_t* tile_base = c->mem.get_n<int64_t>(ntiles + 1);
-        const int64_t again = cstm_exclusive_scan_i64(c->ctx, tile_cnt, tile_base, ntiles, s);
-        CSTM_REQUIRE(again == el.entries, CSTM_EDEVICE, "candidate list counts disagree");
-        k_list_fill<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank, key, c->cnt0[to],
-                                                              loc[to], tile_base, el.adj, el.adj_gid);
-        HIP_TRY(hipGetLastError());
-        later.push_back(tile_base);
-    }
-    // the last reader of tile_cnt was the scan above, which waited for the stream
-    c->mem.release(tile_cnt);
-}
+int64_t tiles_of(int64_t bound) { return (bound + kTile - 1) / kTile + 1; }
 
+// The device size table of one build: per query vertex its top-down set size,
+// refined set size and row entries; per candidate list its entries.
+constexpr int kNsz = 0, kNfin = CSTM_MAX_K, kRtot = 2 * CSTM_MAX_K, kLent = 3 * CSTM_MAX_K;
+constexpr int kMetaSlots = 4 * CSTM_MAX_K + CSTM_MAX_NT;
+
+__global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
+
+}  // namespace
+
+// One CST build: the query's tree and order on the host, every set and list on
+// the device.  Temporaries live in `tmp` until the last wait.
 static void build_cst(cstm_cst* c, const QueryPrep& q) {
     const cstm_graph* g = c->g;
     hipStream_t s = c->stream;
@@ -489,93 +525,161 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     for (int a = 0; a < k; ++a)
         for (int b = a + 1; b < k; ++b)
             if ((q.adj[a] >> b & 1u) && c->parent[a] != b && c->parent[b] != a) c->nontree.push_back({a, b});
-
     for (int u = 0; u < k; ++u)
         if (c->cnt0[u] == 0) c->empty = true;
 
-    int32_t* loc[CSTM_MAX_K] = {};
-    if (!c->empty) {
-        int64_t max_cnt0 = 0;
-        for (int u = 0; u < k; ++u) max_cnt0 = std::max(max_cnt0, c->cnt0[u]);
-        int32_t* scan = c->mem.get_n<int32_t>(max_cnt0 + 1);
-        int32_t* flag = c->mem.get_n<int32_t>(max_cnt0 + 1);
-        int64_t* fdeg = c->mem.get_n<int64_t>(max_cnt0 + 1);
-        int64_t* frow = c->mem.get_n<int64_t>(max_cnt0 + 1);
-        // 1. root candidates: the filtered prefix of the root's label group
-        loc[root] = c->mem.get_n<int32_t>(c->cnt0[root]);
-        c->cand[root] = c->mem.get_n<int32_t>(c->cnt0[root]);
-        c->ncand[root] = c->cnt0[root];
-        k_iota_root<<<cstm_blocks(c->cnt0[root], 256, 4096), 256, 0, s>>>(loc[root], c->cnt0[root],
-                                                                          g->perm + c->lb_lo[root], c->cand[root]);
-        HIP_TRY(hipGetLastError());
-        // 2. top-down construction
-        for (int t = 1; t < k && !c->empty; ++t) {
-            int u = c->bfs[t], up = c->parent[u];
-            loc[u] = c->mem.get_n<int32_t>(c->cnt0[u]);
-            HIP_TRY(hipMemsetAsync(loc[u], 0, c->cnt0[u] * sizeof(int32_t), s));
-            const Rows R = flat_rows(c, c->cand[up], c->ncand[up], fdeg, frow);
-            if (R.total) {
-                k_mark<<<tile_grid(R.total), kWaveBlock, 0, s>>>(R, g->row_ptr, g->col, g->lab_rank,
-                                                                 (uint64_t)q.qlabel[u] << 32, c->cnt0[u], loc[u]);
-                HIP_TRY(hipGetLastError());
-            }
-            int64_t nu = cstm_exclusive_scan_i32(c->ctx, loc[u], scan, c->cnt0[u], s);
-            c->ncand[u] = nu;
-            c->cand[u] = c->mem.get_n<int32_t>(nu ? nu : 1);
-            k_assign<<<cstm_blocks(c->cnt0[u], 256, 4096), 256, 0, s>>>(loc[u], scan, c->cnt0[u],
-                                                                        g->perm + c->lb_lo[u], c->cand[u]);
-            HIP_TRY(hipGetLastError());
-            if (nu == 0) c->empty = true;
-        }
-        // 3. bottom-up refinement
-        for (int t = k - 1; t >= 0 && !c->empty; --t) {
-            int u = c->bfs[t];
-            ChildSet ch{};
-            for (int w = 0; w < k; ++w) {
-                if (c->parent[w] == u) {
-                    ch.c[ch.n].key = (uint64_t)q.qlabel[w] << 32;
-                    ch.c[ch.n].cnt0 = c->cnt0[w];
-                    ch.c[ch.n].loc = loc[w];
-                    ch.n++;
-                }
-            }
-            if (ch.n == 0) continue;
-            int64_t n = c->ncand[u];
-            k_valid<<<wave_grid(n), kWaveBlock, 0, s>>>(c->cand[u], n, g->row_ptr, g->col, g->lab_rank, ch, flag);
-            HIP_TRY(hipGetLastError());
-            int64_t nn = cstm_exclusive_scan_i32(c->ctx, flag, scan, n, s);
-            if (nn != n) {
-                int32_t* cn = c->mem.get_n<int32_t>(nn ? nn : 1);
-                k_refine<<<cstm_blocks(n, 256, 4096), 256, 0, s>>>(c->cand[u], flag, scan, n, g->lab_rank,
-                                                                   (uint64_t)q.qlabel[u] << 32, loc[u], cn);
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(hipStreamSynchronize(s));
-                c->mem.release(c->cand[u]);
-                c->cand[u] = cn;
-                c->ncand[u] = nn;
-            }
-            if (nn == 0) c->empty = true;
-        }
-        c->mem.release(flag);
-        c->mem.release(scan);
-        c->mem.release(fdeg);
-        c->mem.release(frow);
-    }
+    // host bounds from the label index: C(u) lies in the filtered prefix of
+    // its label group, so that prefix bounds its size and its degree sum
+    // bounds the entries of its rows
+    int64_t rbound[CSTM_MAX_K];
+    for (int u = 0; u < k; ++u)
+        rbound[u] = c->cnt0[u] ? g->deg_prefix[c->lb_lo[u] + c->cnt0[u]] - g->deg_prefix[c->lb_lo[u]] : 0;
+    const bool k32 = g->key32 != nullptr;
+    auto key_base = [&](int u) { return (uint64_t)q.qlabel[u] << g->key_shift; };
 
-    // 4a. tree lists (longest-list slots: tree edges by child, then non-tree edges)
+    DevArena tmp;
+    tmp.ctx = c->ctx;
+    // destroyed before tmp: a failed build lets its kernels finish before their blocks go back
+    struct WaitOnExit {
+        hipStream_t s;
+        ~WaitOnExit() { (void)hipStreamSynchronize(s); }
+    } wait_on_exit{s};
+    int64_t* meta = tmp.get_n<int64_t>(kMetaSlots);
+    cstm_fill_words(meta, kMetaSlots * sizeof(int64_t), 0u, s);
+    int64_t* part = tmp.get_n<int64_t>(kScanPartSlots);  // scan scratch; every scan runs on this one stream
     const int n_slots = k + (int)c->nontree.size();
-    int* d_max = c->mem.get_n<int>(n_slots);
-    HIP_TRY(hipMemsetAsync(d_max, 0, (size_t)n_slots * sizeof(int), s));
-    std::vector<void*> later;
-    int64_t maxn = 1;
-    for (int u = 0; u < k; ++u) maxn = std::max(maxn, c->ncand[u]);
-    int64_t* d_cnt = c->mem.get_n<int64_t>(maxn + 1);
-    int64_t* l_deg = c->mem.get_n<int64_t>(maxn + 1);
-    int64_t* l_row = c->mem.get_n<int64_t>(maxn + 1);
+    int* d_max = tmp.get_n<int>(n_slots);
+    cstm_fill_words(d_max, (size_t)n_slots * sizeof(int), 0u, s);
+    auto nsz = [&](int u) { return meta + kNsz + u; };
+    auto nfin = [&](int u) { return meta + kNfin + u; };
+
+    int32_t* loc[CSTM_MAX_K] = {};     // rank table: rank -> index in C(u), or -1
+    int32_t* cand_td[CSTM_MAX_K] = {}; // top-down set (bound-sized)
+    int32_t* tdrank[CSTM_MAX_K] = {};  // rank of each top-down candidate
+    int32_t* cand_fin[CSTM_MAX_K] = {};  // refined set (top-down set for leaves)
+    int32_t* newidx[CSTM_MAX_K] = {};  // top-down index -> refined index (nullptr: identity)
+    int64_t* rowoff[CSTM_MAX_K] = {};  // row offsets of the top-down set
+    int32_t* erank[CSTM_MAX_K] = {};   // by tree child: kept ranks over the parent's rows
+    auto rows_of = [&](int u) { return Rows{cand_td[u], rowoff[u], nsz(u)}; };
+    auto ensure_rows = [&](int u) {
+        if (rowoff[u]) return;
+        int64_t* deg = tmp.get_n<int64_t>(c->cnt0[u] + 1);
+        rowoff[u] = tmp.get_n<int64_t>(c->cnt0[u] + 1);
+        k_cand_degrees<<<cstm_blocks(c->cnt0[u], 256, 4096), 256, 0, s>>>(cand_td[u], nsz(u), g->row_ptr, deg);
+        HIP_TRY(hipGetLastError());
+        cstm_dscan_i64(deg, rowoff[u], nsz(u), c->cnt0[u], meta + kRtot + u, part, s);
+    };
+
+    // tree lists: per child, the offsets over the refined parent set (bound-sized) and the tile bases
+    int64_t* toff_b[CSTM_MAX_K] = {};
+    int64_t* tbase[CSTM_MAX_K] = {};
     if (!c->empty) {
+        // 1. root candidates: the filtered prefix of the root's label group
+        const int64_t c0r = c->cnt0[root];
+        loc[root] = tmp.get_n<int32_t>(c0r);
+        cand_td[root] = tmp.get_n<int32_t>(c0r);
+        tdrank[root] = tmp.get_n<int32_t>(c0r);
+        k_iota_root<<<cstm_blocks(c0r, 256, 4096), 256, 0, s>>>(loc[root], c0r, g->perm + c->lb_lo[root],
+                                                                cand_td[root], tdrank[root]);
+        HIP_TRY(hipGetLastError());
+        k_set_i64<<<1, 1, 0, s>>>(nsz(root), c0r);
+        HIP_TRY(hipGetLastError());
+        // 2. top-down construction, keeping each entry's rank test
         for (int t = 1; t < k; ++t) {
-            int u = c->bfs[t];
-            build_lists(c, c->parent[u], u, loc, c->tree[u], d_max + u, l_deg, l_row, d_cnt, false, later);
+            const int u = c->bfs[t], up = c->parent[u];
+            const int64_t c0 = c->cnt0[u];
+            ensure_rows(up);
+            loc[u] = tmp.get_n<int32_t>(c0);
+            cstm_fill_words(loc[u], (size_t)c0 * 4, 0u, s);
+            erank[u] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[up], 1));
+            if (k32)
+                k_mark<uint32_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(
+                    rows_of(up), g->row_ptr, g->col, g->key32, (uint32_t)key_base(u), c0, loc[u], erank[u]);
+            else
+                k_mark<uint64_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(
+                    rows_of(up), g->row_ptr, g->col, g->key64, key_base(u), c0, loc[u], erank[u]);
+            HIP_TRY(hipGetLastError());
+            int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
+            cstm_dscan_i32(loc[u], scan, nullptr, c0, nsz(u), part, s);
+            cand_td[u] = tmp.get_n<int32_t>(c0);
+            tdrank[u] = tmp.get_n<int32_t>(c0);
+            k_assign<<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(loc[u], scan, c0, g->perm + c->lb_lo[u], cand_td[u],
+                                                                tdrank[u]);
+            HIP_TRY(hipGetLastError());
+        }
+        // 3. bottom-up refinement, children first, from the kept ranks
+        for (int t = k - 1; t >= 0; --t) {
+            const int u = c->bfs[t];
+            ChildSet ch{};
+            for (int w = 0; w < k; ++w)
+                if (c->parent[w] == u) ch.c[ch.n++] = ChildRef{erank[w], loc[w]};
+            if (ch.n == 0) {
+                cand_fin[u] = cand_td[u];
+                k_copy_i64<<<1, 1, 0, s>>>(nsz(u), nfin(u));
+                HIP_TRY(hipGetLastError());
+                continue;
+            }
+            const int64_t c0 = c->cnt0[u];
+            int32_t* flag = tmp.get_n<int32_t>(c0 + 1);
+            k_valid<<<wave_grid(c0), kWaveBlock, 0, s>>>(rows_of(u), ch, flag);
+            HIP_TRY(hipGetLastError());
+            int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
+            cstm_dscan_i32(flag, scan, nsz(u), c0, nfin(u), part, s);
+            cand_fin[u] = tmp.get_n<int32_t>(c0);
+            newidx[u] = tmp.get_n<int32_t>(c0);
+            k_refine<<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(cand_td[u], tdrank[u], flag, scan, nsz(u), loc[u],
+                                                                cand_fin[u], newidx[u]);
+            HIP_TRY(hipGetLastError());
+        }
+        // 4a. tree list sizes (parent -> child), from the kept ranks
+        for (int t = 1; t < k; ++t) {
+            const int u = c->bfs[t], p = c->parent[u];
+            const int64_t c0p = c->cnt0[p], nt = tiles_of(rbound[p]);
+            unsigned long long* cnt = tmp.get_n<unsigned long long>(c0p + 1);
+            int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
+            cstm_fill_words(cnt, (size_t)(c0p + 1) * 8, 0u, s);
+            cstm_fill_words(tcnt, (size_t)(nt + 1) * 8, 0u, s);
+            k_tree_count<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(rows_of(p), newidx[p], erank[u], loc[u], cnt, tcnt);
+            HIP_TRY(hipGetLastError());
+            toff_b[u] = tmp.get_n<int64_t>(c0p + 1);
+            cstm_dscan_i64((const int64_t*)cnt, toff_b[u], nfin(p), c0p, meta + kLent + u, part, s);
+            tbase[u] = tmp.get_n<int64_t>(nt + 1);
+            cstm_dscan_i64(tcnt, tbase[u], nullptr, nt, nullptr, part, s);
+        }
+    }
+    // wait 1: the refined set sizes and the tree list sizes
+    std::vector<int64_t> hm(kMetaSlots, 0);
+    HIP_TRY(hipMemcpyAsync(hm.data(), meta, kMetaSlots * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!c->empty) {
+        for (int u = 0; u < k; ++u) {
+            c->ncand[u] = hm[kNfin + u];
+            if (c->ncand[u] == 0) c->empty = true;
+        }
+        // a set emptied by the refinement leaves no embedding: keep no candidates at all
+        if (c->empty)
+            for (int u = 0; u < k; ++u) c->ncand[u] = 0;
+    }
+    if (!c->empty) {
+        // the kept arrays at their exact sizes
+        for (int u = 0; u < k; ++u) {
+            c->cand[u] = c->mem.get_n<int32_t>(c->ncand[u]);
+            HIP_TRY(hipMemcpyAsync(c->cand[u], cand_fin[u], (size_t)c->ncand[u] * 4, hipMemcpyDeviceToDevice, s));
+        }
+        for (int t = 1; t < k; ++t) {
+            const int u = c->bfs[t], p = c->parent[u];
+            EdgeLists& el = c->tree[u];
+            el.from = -1;
+            el.to = -1;
+            el.entries = hm[kLent + u];
+            el.off = c->mem.get_n<int64_t>(c->ncand[p] + 1);
+            HIP_TRY(hipMemcpyAsync(el.off, toff_b[u], (size_t)(c->ncand[p] + 1) * 8, hipMemcpyDeviceToDevice, s));
+            el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
+            k_tree_fill<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(rows_of(p), newidx[p], erank[u], loc[u], tbase[u],
+                                                                    el.adj);
+            HIP_TRY(hipGetLastError());
+            k_max_len<<<cstm_blocks(c->ncand[p], 256, 1024), 256, 0, s>>>(el.off, c->ncand[p], d_max + u);
+            HIP_TRY(hipGetLastError());
         }
     }
     // 4b. matching order: the caller's (checked against the tree) or the path-based one
@@ -592,7 +696,9 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         }
         for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
     } else {
-        std::vector<std::pair<std::pair<uint64_t, int>, std::vector<int>>> paths;
+        // root-to-leaf paths and their numbers of CST path embeddings, all
+        // computed before one wait
+        std::vector<std::vector<int>> plist;
         for (int leaf = 0; leaf < k; ++leaf) {
             bool has_child = false;
             for (int w = 0; w < k; ++w) has_child |= c->parent[w] == leaf;
@@ -600,39 +706,48 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             std::vector<int> p{leaf};
             while (c->parent[p.back()] >= 0) p.push_back(c->parent[p.back()]);
             std::reverse(p.begin(), p.end());
-            uint64_t cnt = 0;
-            if (!c->empty) {
-                const uint64_t* child_val = nullptr;
-                uint64_t* vals[CSTM_MAX_K] = {};
-                for (int i = (int)p.size() - 2; i >= 0; --i) {
-                    int u = p[i], uc = p[i + 1];
-                    vals[i] = c->mem.get_n<uint64_t>(c->ncand[u] ? c->ncand[u] : 1);
-                    k_path_step<<<cstm_blocks(c->ncand[u], 256, 4096), 256, 0, s>>>(
-                        c->tree[uc].off, c->tree[uc].adj, c->ncand[u], child_val, vals[i]);
-                    HIP_TRY(hipGetLastError());
-                    child_val = vals[i];
-                }
-                unsigned long long* tot = (unsigned long long*)d_cnt;
-                HIP_TRY(hipMemsetAsync(tot, 0, 8, s));
-                if (p.size() == 1) {
-                    cnt = (uint64_t)c->ncand[p[0]];
-                } else {
-                    k_sum_sat<<<cstm_blocks(c->ncand[root], 256, 1024), 256, 0, s>>>(vals[0], c->ncand[root], tot);
-                    HIP_TRY(hipGetLastError());
-                    HIP_TRY(hipMemcpyAsync(&cnt, tot, 8, hipMemcpyDeviceToHost, s));
-                    HIP_TRY(hipStreamSynchronize(s));
-                }
-                for (int i = 0; i < (int)p.size(); ++i)
-                    if (vals[i]) c->mem.release(vals[i]);
-            }
-            paths.push_back({{cnt, leaf}, p});
+            plist.push_back(p);
         }
-        std::sort(paths.begin(), paths.end(),
-                  [](const auto& x, const auto& y) { return x.first < y.first; });
+        const int np = (int)plist.size();
+        unsigned long long* d_paths = tmp.get_n<unsigned long long>(std::max(np, 1));
+        cstm_fill_words(d_paths, (size_t)std::max(np, 1) * 8, 0u, s);
+        std::vector<uint64_t> pcnt((size_t)np, 0);
+        if (!c->empty) {
+            for (int pi = 0; pi < np; ++pi) {
+                const std::vector<int>& p = plist[pi];
+                if (p.size() == 1) {
+                    pcnt[pi] = (uint64_t)c->ncand[p[0]];
+                    continue;
+                }
+                const uint64_t* child_val = nullptr;
+                for (int i = (int)p.size() - 2; i >= 0; --i) {
+                    const int u = p[i], uc = p[i + 1];
+                    uint64_t* vals = tmp.get_n<uint64_t>(c->ncand[u] ? c->ncand[u] : 1);
+                    k_path_step<<<cstm_blocks(c->ncand[u], 256, 4096), 256, 0, s>>>(
+                        c->tree[uc].off, c->tree[uc].adj, c->ncand[u], child_val, vals);
+                    HIP_TRY(hipGetLastError());
+                    child_val = vals;
+                }
+                k_sum_sat<<<cstm_blocks(c->ncand[root], 256, 1024), 256, 0, s>>>(child_val, c->ncand[root],
+                                                                                   d_paths + pi);
+                HIP_TRY(hipGetLastError());
+            }
+            // wait 2: the path counts
+            std::vector<unsigned long long> hp((size_t)std::max(np, 1));
+            HIP_TRY(hipMemcpyAsync(hp.data(), d_paths, hp.size() * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (int pi = 0; pi < np; ++pi)
+                if (plist[pi].size() > 1) pcnt[pi] = hp[pi];
+        }
+        std::vector<int> idx((size_t)np);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+            return pcnt[x] != pcnt[y] ? pcnt[x] < pcnt[y] : plist[x].back() < plist[y].back();
+        });
         int n = 0;
         uint32_t placed = 0;
-        for (auto& pr : paths)
-            for (int u : pr.second)
+        for (int pi : idx)
+            for (int u : plist[pi])
                 if (!(placed >> u & 1u)) {
                     placed |= 1u << u;
                     c->order[n++] = u;
@@ -640,7 +755,9 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         if (n == 0) c->order[n++] = root;
         for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
     }
-    // 4c. non-tree candidate edges, earlier -> later in the order
+    // 4c. non-tree candidate edges, earlier -> later in the order: sizes, one wait, fills
+    std::vector<int32_t*> ntE(c->nontree.size(), nullptr);
+    std::vector<int64_t*> ntbase(c->nontree.size(), nullptr);
     for (size_t j = 0; j < c->nontree.size(); ++j) {
         int a = c->nontree[j].first, b = c->nontree[j].second;
         if (c->pos_of[a] > c->pos_of[b]) std::swap(a, b);
@@ -648,13 +765,49 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.from = c->pos_of[a];
         el.to = c->pos_of[b];
         if (!c->empty) {
-            build_lists(c, a, b, loc, el, d_max + k + (int)j, l_deg, l_row, d_cnt, true, later);
+            ensure_rows(a);
+            const int64_t nt = tiles_of(rbound[a]);
+            unsigned long long* cnt = tmp.get_n<unsigned long long>(c->ncand[a] + 1);
+            int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
+            cstm_fill_words(cnt, (size_t)(c->ncand[a] + 1) * 8, 0u, s);
+            cstm_fill_words(tcnt, (size_t)(nt + 1) * 8, 0u, s);
+            ntE[j] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[a], 1));
+            if (k32)
+                k_nt_count<uint32_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
+                    rows_of(a), newidx[a], g->row_ptr, g->col, g->key32, (uint32_t)key_base(b), c->cnt0[b], loc[b],
+                    ntE[j], cnt, tcnt);
+            else
+                k_nt_count<uint64_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
+                    rows_of(a), newidx[a], g->row_ptr, g->col, g->key64, key_base(b), c->cnt0[b], loc[b], ntE[j], cnt,
+                    tcnt);
+            HIP_TRY(hipGetLastError());
+            el.off = c->mem.get_n<int64_t>(c->ncand[a] + 1);
+            cstm_dscan_i64((const int64_t*)cnt, el.off, nullptr, c->ncand[a], meta + kLent + k + (int)j, part, s);
+            ntbase[j] = tmp.get_n<int64_t>(nt + 1);
+            cstm_dscan_i64(tcnt, ntbase[j], nullptr, nt, nullptr, part, s);
+            k_max_len<<<cstm_blocks(c->ncand[a], 256, 1024), 256, 0, s>>>(el.off, c->ncand[a], d_max + k + (int)j);
+            HIP_TRY(hipGetLastError());
         } else {
             el.off = nullptr;
         }
         c->nt.push_back(el);
     }
-    // longest lists: one read-back for every edge (also the wait for the fills)
+    if (!c->empty && !c->nontree.empty()) {
+        // wait 3: the non-tree list sizes
+        HIP_TRY(hipMemcpyAsync(hm.data(), meta, kMetaSlots * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t j = 0; j < c->nontree.size(); ++j) {
+            EdgeLists& el = c->nt[j];
+            int a = c->order[el.from];
+            el.entries = hm[kLent + k + (int)j];
+            el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
+            el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
+            k_nt_fill<<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(rows_of(a), g->row_ptr, g->col, ntE[j], ntbase[j],
+                                                                  el.adj, el.adj_gid);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    // wait 4: the longest lists (and every fill before the temporaries go back)
     {
         std::vector<int> h((size_t)n_slots, 0);
         HIP_TRY(hipMemcpyAsync(h.data(), d_max, (size_t)n_slots * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -670,18 +823,10 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
                 c->d_cst = std::max(c->d_cst, c->nt[j].max_len);
             }
         }
-        for (void* p : later) c->mem.release(p);
     }
     std::sort(c->nt.begin(), c->nt.end(), [](const EdgeLists& x, const EdgeLists& y) {
         return x.to != y.to ? x.to < y.to : x.from < y.from;
     });
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int u = 0; u < k; ++u)
-        if (loc[u]) c->mem.release(loc[u]);
-    c->mem.release(d_cnt);
-    c->mem.release(l_deg);
-    c->mem.release(l_row);
-    c->mem.release(d_max);
 
     // descriptor in order positions
     CstDev& D = c->host_desc;
@@ -726,6 +871,8 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     c->bytes = bytes;
     HIP_TRY(hipStreamSynchronize(s));
 }
+
+
 
 extern "C" cstm_status cstm_cst_build_ordered(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
                                               int32_t m_q, const int32_t* qedges, const int32_t* order, void* stream,

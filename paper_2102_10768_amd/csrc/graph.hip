@@ -5,8 +5,9 @@
 // by label and orders each group by degree descending, then id ascending, so
 // that the label-and-degree candidate filter of a query vertex u
 // (l(v) = l(u), d(v) >= d_q(u)) is a prefix of u's label group, and a vertex's
-// rank inside its group decides membership in one comparison.
-#include <hipcub/hipcub.hpp>
+// rank inside its group decides membership in one comparison.  The index is
+// built with the library's own radix sort and scan (prims.hip).
+#include <algorithm>
 
 #include "internal.h"
 
@@ -88,15 +89,17 @@ __global__ void k_check_edges(const int64_t* __restrict__ row_ptr, const int32_t
     if (bad) atomicOr(err, bad);
 }
 
+// Sort key of vertex v: label, then degree descending (deg_bits bits hold
+// the degree); the stable sort keeps ids ascending among equal keys.
 __global__ void k_make_keys(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ label, int64_t n,
-                            uint64_t* __restrict__ keys, int32_t* __restrict__ ids,
+                            int deg_bits, uint64_t* __restrict__ keys, int32_t* __restrict__ ids,
                             unsigned long long* __restrict__ hist) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const uint64_t dmax = (1ull << deg_bits) - 1;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        uint64_t d = (uint64_t)(row_ptr[v + 1] - row_ptr[v]);
-        uint64_t l = (uint64_t)label[v];
-        // ascending key = label, then degree descending; the stable sort keeps ids ascending
-        keys[v] = (l << 32) | (0xFFFFFFFFull - (d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d));
+        const uint64_t d = (uint64_t)(row_ptr[v + 1] - row_ptr[v]);
+        const uint64_t l = (uint64_t)label[v];
+        keys[v] = (l << deg_bits) | (dmax - d);
         ids[v] = (int32_t)v;
         atomicAdd(&hist[l], 1ull);
     }
@@ -111,14 +114,22 @@ __global__ void k_perm_degrees(const int64_t* __restrict__ row_ptr, const int32_
     }
 }
 
+// Packed key of every vertex: (label << shift) | rank inside its label group.
+template <class K>
 __global__ void k_ranks(const int32_t* __restrict__ perm, const int32_t* __restrict__ label,
-                        const int64_t* __restrict__ label_ptr, int64_t n, uint64_t* __restrict__ lab_rank) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+                        const int64_t* __restrict__ label_ptr, int64_t n, int shift, K* __restrict__ key) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int32_t v = perm[i];
-        uint64_t l = (uint64_t)label[v];
-        lab_rank[v] = (l << 32) | (uint64_t)(i - label_ptr[l]);
+        const int32_t v = perm[i];
+        const int32_t l = label[v];
+        key[v] = (K)(((K)l << shift) | (K)(i - label_ptr[l]));
     }
+}
+
+static int bits_for(uint64_t x) {  // bits needed to hold every value in [0, x]
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
 }
 
 // deg_at_least[l][d]: the label groups are degree-descending, so a binary search finds the cut.
@@ -207,58 +218,61 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
         const int32_t L = g->num_labels;
         // label index
         g->perm = g->mem.get_n<int32_t>(n ? n : 1);
-        g->lab_rank = g->mem.get_n<uint64_t>(n ? n : 1);
         g->label_ptr.assign((size_t)L + 1, 0);
         g->deg_at_least.assign((size_t)(L > 0 ? L : 0) * (CSTM_MAX_K + 1), 0);
+        g->deg_prefix.assign((size_t)n + 1, 0);
         if (n > 0) {
             uint64_t* keys = g->mem.get_n<uint64_t>(n);
-            uint64_t* keys2 = g->mem.get_n<uint64_t>(n);
-            int32_t* ids = g->mem.get_n<int32_t>(n);
+            int32_t* ids = g->perm;  // sorted in place into the permutation
             unsigned long long* hist = g->mem.get_n<unsigned long long>(L);
-            HIP_TRY(hipMemsetAsync(hist, 0, (size_t)L * 8, s));
-            k_make_keys<<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->row_ptr, g->label, n, keys, ids, hist);
+            cstm_fill_words(hist, (size_t)L * 8, 0u, s);
+            const int deg_bits = std::max(1, bits_for((uint64_t)g->max_degree));
+            const int label_bits = bits_for((uint64_t)(L - 1));
+            k_make_keys<<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->row_ptr, g->label, n, deg_bits, keys, ids, hist);
             HIP_TRY(hipGetLastError());
-            int end_bit = 32;
-            while (end_bit < 64 && ((uint64_t)L >> (end_bit - 32)) > 0) ++end_bit;
-            size_t tb = 0;
-            std::lock_guard<std::mutex> lk(ctx->scratch_mu);
-            HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys2, ids, g->perm, (int)n, 0, end_bit, s));
-            void* tmp = ctx->scratch(tb);
-            HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys, keys2, ids, g->perm, (int)n, 0, end_bit, s));
+            cstm_radix_sort_pairs(ctx, keys, ids, n, deg_bits + label_bits, s);
             std::vector<unsigned long long> h((size_t)L);
             HIP_TRY(hipMemcpyAsync(h.data(), hist, (size_t)L * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            for (int32_t l = 0; l < L; ++l) g->label_ptr[l + 1] = g->label_ptr[l] + (int64_t)h[l];
+            int64_t max_group = 0;
+            for (int32_t l = 0; l < L; ++l) {
+                g->label_ptr[l + 1] = g->label_ptr[l] + (int64_t)h[l];
+                max_group = std::max<int64_t>(max_group, (int64_t)h[l]);
+            }
             int64_t* lp = g->mem.get_n<int64_t>((size_t)L + 1);
             HIP_TRY(hipMemcpyAsync(lp, g->label_ptr.data(), ((size_t)L + 1) * 8, hipMemcpyHostToDevice, s));
-            k_ranks<<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->perm, g->label, lp, n, g->lab_rank);
+            // packed (label, rank) keys: 32 bits when both fit
+            const int rank_bits = std::max(1, bits_for((uint64_t)(max_group - 1)));
+            if (label_bits + rank_bits <= 32) {
+                g->key_shift = rank_bits;
+                g->key32 = g->mem.get_n<uint32_t>(n);
+                k_ranks<uint32_t><<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->perm, g->label, lp, n, rank_bits,
+                                                                             g->key32);
+            } else {
+                g->key_shift = 32;
+                g->key64 = g->mem.get_n<uint64_t>(n);
+                k_ranks<uint64_t><<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->perm, g->label, lp, n, 32, g->key64);
+            }
             HIP_TRY(hipGetLastError());
             int64_t* dal = g->mem.get_n<int64_t>(g->deg_at_least.size());
             k_deg_at_least<<<cstm_blocks((int64_t)g->deg_at_least.size(), 256, 4096), 256, 0, s>>>(
                 g->row_ptr, g->perm, lp, L, dal);
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipMemcpyAsync(g->deg_at_least.data(), dal, g->deg_at_least.size() * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            // degree prefix sums in label-index order, for footprint estimates
+            // degree prefix sums in label-index order, for footprint estimates and build bounds
             int64_t* pd = (int64_t*)keys;  // n int64 entries, free again
-            int64_t* ps = (int64_t*)keys2;
+            int64_t* ps = g->mem.get_n<int64_t>(n + 1);
+            int64_t* part = g->mem.get_n<int64_t>(kScanPartSlots);
             k_perm_degrees<<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->row_ptr, g->perm, n, pd);
             HIP_TRY(hipGetLastError());
+            cstm_dscan_i64(pd, ps, nullptr, n, nullptr, part, s);
+            HIP_TRY(hipMemcpyAsync(g->deg_prefix.data(), ps, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            g->deg_prefix.assign((size_t)n + 1, 0);
-            {
-                size_t tb2 = 0;
-                HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, pd, ps, (int)n, s));
-                void* tmp2 = ctx->scratch(tb2);
-                HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp2, tb2, pd, ps, (int)n, s));
-                HIP_TRY(hipMemcpyAsync(g->deg_prefix.data() + 1, ps, (size_t)n * 8, hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-            }
             g->mem.release(keys);
-            g->mem.release(keys2);
-            g->mem.release(ids);
             g->mem.release(hist);
             g->mem.release(dal);
+            g->mem.release(ps);
+            g->mem.release(part);
         }
         *out = g;
     });
@@ -291,20 +305,28 @@ extern "C" cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const i
                 sdeg[u] = (uint64_t)(g->deg_prefix[lo + c0[u]] - g->deg_prefix[lo]);
             }
             if ((uint64_t)c0[u] > max_c0) max_c0 = (uint64_t)c0[u];
-            // candidate array and rank table (C(u) is a subset of the filtered label prefix)
-            bytes += 8ull * (uint64_t)c0[u];
+            // kept: the candidate array; during the build: rank table, top-down
+            // set and ranks, refined set, index map, flags and their scan (int32
+            // each), row degrees and offsets (int64 each)
+            bytes += 4ull * (uint64_t)c0[u] + (7ull * 4 + 2ull * 8) * ((uint64_t)c0[u] + 1);
         }
-        // scan, flag, per-owner counts and the path-count vectors of one leaf path
-        bytes += (24ull + 8ull * (uint64_t)k) * (max_c0 + 1);
-        // every candidate edge list: offsets over its owner, entries (ids and, for
-        // non-tree lists, global ids); an edge (v, w) with v in C(a), w in C(b)
-        // appears once, so either side's degree sum bounds the entries
+        // path-count vectors of one leaf path
+        bytes += 8ull * (uint64_t)k * (max_c0 + 1);
+        // every candidate edge list: kept offsets over its owner and entries (ids
+        // and, for non-tree lists, global ids); an edge (v, w) with v in C(a), w
+        // in C(b) appears once, so either side's degree sum bounds the entries.
+        // During the build: per-owner counts and offsets (int64 each) and one
+        // int32 per row entry of the owner's candidates (kept ranks or indices),
+        // plus two int64 per tile of those rows.
         for (int e = 0; e < m_q; ++e) {
             int a = qedges[2 * e], b = qedges[2 * e + 1];
             uint64_t ent = sdeg[a] < sdeg[b] ? sdeg[a] : sdeg[b];
+            const uint64_t rows = sdeg[a] > sdeg[b] ? sdeg[a] : sdeg[b];
+            const uint64_t cmax = (uint64_t)(c0[a] > c0[b] ? c0[a] : c0[b]);
             bytes += 8ull * (max_c0 + 1) + 8ull * ent;
+            bytes += 16ull * (cmax + 1) + 4ull * rows + 16ull * (rows / 512 + 2);
         }
-        *bytes_out = bytes + 4096;  // descriptor and small flags
+        *bytes_out = bytes + 65536;  // descriptor, size table, scan scratch and small flags
     });
 }
 

@@ -71,23 +71,18 @@ struct cstm_ctx {
     std::unordered_map<void*, size_t> ws_sizes;
     void* ws_acquire(size_t bytes);
     void ws_release(void* p);
-    // reusable temporary storage for library scans and sorts
-    void* tmp = nullptr;
-    size_t tmp_bytes = 0;
     // cache of freed device blocks by power-of-two size class (hipMalloc path only)
     std::vector<std::vector<void*>> pool;
     std::unordered_map<void*, int> block_class;
     void release_pool();
     // A context may be used from several host threads (e.g. one building CSTs
-    // while others enumerate on their own streams): the block cache, the scan
-    // scratch and the workspace list each have a lock.
+    // while others enumerate on their own streams): the block cache and the
+    // workspace list each have a lock.
     std::mutex pool_mu;
-    std::mutex scratch_mu;  // held for the whole use of `tmp`
-    std::mutex ws_mu;       // workspace list and last_enum
+    std::mutex ws_mu;  // workspace list and last_enum
 
     void* dmalloc(size_t bytes);
     void dfree(void* p);
-    void* scratch(size_t bytes);  // grows ctx-owned temporary storage
 };
 
 // A bag of device allocations released together.
@@ -121,8 +116,12 @@ struct cstm_graph {
     DevArena mem;
     // label index: vertices grouped by label, each group by (degree desc, id asc)
     int32_t* perm = nullptr;
-    // per vertex: (label << 32) | rank inside its label group
-    uint64_t* lab_rank = nullptr;
+    // per vertex: (label << key_shift) | rank inside its label group, packed
+    // into 32 bits when the label and rank bits fit (key32), else 64 bits with
+    // key_shift = 32 (key64); exactly one of the two is set
+    uint32_t* key32 = nullptr;
+    uint64_t* key64 = nullptr;
+    int key_shift = 32;
     std::vector<int64_t> label_ptr;  // host, num_labels + 1
     // host: count of vertices of label l with degree >= d, d = 0..CSTM_MAX_K
     std::vector<int64_t> deg_at_least;
@@ -277,9 +276,22 @@ struct cstm_cst {
 
 // ---------------------------------------------------------------- helpers shared across files
 
-// Exclusive prefix sum of n int64 values into out[0..n]; out[n] = total.  Returns total.
-int64_t cstm_exclusive_scan_i64(cstm_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
-int64_t cstm_exclusive_scan_i32(cstm_ctx* ctx, const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Device-wide exclusive prefix sums (prims.hip): out[0..len) and out[len] =
+// the total, where len = *n_dev when n_dev is given (n is then an upper bound
+// that sizes the launch) and len = n otherwise; *total_out (may be NULL) also
+// receives the total.  part: scratch of kScanPartSlots int64 (one scan at a
+// time per buffer).  Nothing waits for the device.
+constexpr int kScanPartSlots = 1025;
+void cstm_dscan_i64(const int64_t* in, int64_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,
+                    int64_t* part, hipStream_t s);
+void cstm_dscan_i32(const int32_t* in, int32_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,
+                    int64_t* part, hipStream_t s);
+void cstm_dscan_u32(const uint32_t* in, uint32_t* out, int64_t n, int64_t* part, hipStream_t s);
+// Fill bytes / 4 words with value (a kernel, not a memset node).
+void cstm_fill_words(void* p, size_t bytes, uint32_t value, hipStream_t s);
+// Stable ascending sort of (keys, vals) by the low `bits` bits of the keys, in
+// place (8-bit LSD passes); waits for the stream before returning.
+void cstm_radix_sort_pairs(cstm_ctx* ctx, uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
 
 inline unsigned cstm_blocks(int64_t items, int per_block, unsigned cap = 1u << 20) {
     int64_t b = (items + per_block - 1) / per_block;

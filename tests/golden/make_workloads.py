@@ -2,6 +2,7 @@
 
     python tests/golden/make_workloads.py c1
     python tests/golden/make_workloads.py c2 [--budget 200000000] [--count-cap 20000000000]
+    python tests/golden/make_workloads.py c5 [--budget 150000000000] [--threads 0]
 
 Expected values come from the CPU oracle (``oracle``); inputs come only
 from ``synth``.  For the sparse class of c2 the expected count is the exact
@@ -184,6 +185,65 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
     })
 
 
+def make_fixed_draws(w: dict, budget: int, threads: int, unlimited_s: float):
+    """Billion-edge workload: exactly the configured number of random walks
+    (sizes uniform in [k_min, k_max]), every one kept, none redrawn.  Each
+    asks for min(#embeddings, limit); the oracle (label-grouped rows) screens
+    each within node_budget work units.  Queries it finishes get their stored
+    count; the others are recorded as INF (no count) and stay out of parity."""
+    t_start = time.time()
+    g = make_graph(w["graph"], log=lambda m: print(m, flush=True))
+    print("graph", g.summary(), f"({time.time() - t_start:.0f}s)", flush=True)
+    lcol = oracle.label_grouped_col(g, threads=threads)
+    spec = w["queries"]
+    rng = _rng(spec["seed"], STREAM_QUERIES)
+    limit = int(spec["limit"])
+    qs = []
+    for _ in range(int(spec["count"])):
+        k = int(rng.integers(int(spec["k_min"]), int(spec["k_max"]) + 1))
+        qs.append(random_walk_query(g, k, rng))
+    # first, without the limit: does any query finish within unlimited_s seconds?
+    unlimited = []
+    for i, q in enumerate(qs):
+        if unlimited_s <= 0:
+            break
+        r = oracle.match(g, q, deadline_s=unlimited_s, threads=threads, lcol=lcol)
+        unlimited.append({"finished": r.status == oracle.OK, "count_at_stop": r.count})
+        print(f"unlimited query {i}: {'finished' if r.status == oracle.OK else 'INF'} {r.count}", flush=True)
+    out, inf = [], []
+    oracle_s = 0.0
+    for i, q in enumerate(qs):
+        t = time.time()
+        r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol, limit=limit)
+        dt = time.time() - t
+        oracle_s += dt
+        d = q.to_dict()
+        d.update(draw=i, qid=i, nodes=r.nodes, oracle_s=round(dt, 3), limit=limit)
+        if r.status == oracle.OK:
+            d.update(count=r.count, expected_from="oracle")
+        else:
+            d.update(count=None, partial=r.count, expected_from="INF")
+            inf.append(i)
+        out.append(d)
+        print(f"query {i} k={q.k} m_q={q.m_q}: {'INF' if d['count'] is None else d['count']} "
+              f"in {dt:.1f}s ({len(inf)} INF so far)", flush=True)
+    write(w["name"], {
+        "workload": w,
+        "graph_summary": g.summary(),
+        "screen": {"rule": f"every drawn query kept; the oracle (label-grouped rows) must reach min(total, {limit}) "
+                           "within node_budget work units, else the query is INF and has no stored count",
+                   "node_budget": budget, "inf": inf, "oracle_seconds": round(oracle_s, 1),
+                   "unlimited_screen": {"seconds_per_query": unlimited_s,
+                                        "finished": sum(u["finished"] for u in unlimited),
+                                        "tried": len(unlimited),
+                                        "min_count_at_stop": min((u["count_at_stop"] for u in unlimited), default=None),
+                                        "max_count_at_stop": max((u["count_at_stop"] for u in unlimited), default=None)},
+                   "seconds": round(time.time() - t_start, 1)},
+        "oracle": {"threads": threads or oracle.num_cores()},
+        "queries": out,
+    })
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("name", choices=sorted(ALL))
@@ -192,9 +252,13 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--count-cap", type=int, default=20_000_000_000)
     ap.add_argument("--dense-tries", type=int, default=100)
+    ap.add_argument("--unlimited-s", type=float, default=2.0,
+                    help="c5: seconds of an unlimited oracle run per query before the limited screen (0: skip)")
     a = ap.parse_args()
     w = ALL[a.name]
-    if "sizes" in w["queries"]:
+    if w["name"] == "c5":
+        make_fixed_draws(w, a.budget if a.budget != 200_000_000 else 150_000_000_000, a.threads, a.unlimited_s)
+    elif "sizes" in w["queries"]:
         make_small(w)
     elif "k_min" in w["queries"]:
         make_batch(w, a.budget, a.max_draws, a.threads)
