@@ -1,27 +1,33 @@
 """Benchmark: embeddings/sec of CST subgraph matching on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2] [--no-autotune]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c5] [--extras c2,c3]
 
-One step runs the whole matching path for every query of the workload: CST
-construction on the device, the partition check, and enumeration (counting).
-The plain form issues one query per launch with the library's default launch
-parameters; the batched form (reported beside it) builds all CSTs and counts
-them in one persistent launch, with launch parameters chosen by the autotuner
-on a seeded calibration subset.  Counts are checked against the expected
-values stored with the workload.  The graph is generated from its seed and
-made resident before timing starts.
+The main line is the batched form of the billion-edge R-MAT workload (the
+largest configuration that fits one GPU): one step builds the CST of every
+query of the stored set (on several streams at once) and counts them all in
+one persistent launch over a device task queue; each query counts
+min(#embeddings, its stored limit), and every count is checked against the
+value the CPU oracle stored with the workload.  The plain form (one query per
+launch) runs beside it on the same queries, with the enumeration kernel's
+roofline and the oracle timed on the host cores.  Other stored workloads
+(--extras) report their plain and batched forms as extra keys.  Graphs are
+generated from their seeds and made resident before timing starts.
 
-Prints one JSON line (see the keys below); exits 1 if a count is wrong.
+Prints one JSON line; exits 1 if a count is wrong.
 
     python bench.py --workload c2 --share 0,0.01,0.1 [--host-threads 16]
 
 sweeps the host-core share of Algorithm 3 instead (CSTs built beforehand, one
-JSON line per delta, counts checked), and
+JSON line per delta, counts checked),
 
     python bench.py --workload c2 --orders 6
 
 times each query under its path-based order and random tree orders (Section
-VII-C's BEST/AVG/WORST).
+VII-C's BEST/AVG/WORST), and
+
+    python bench.py --workload c4 --serve [--rates 50,200,800]
+
+runs the request-serving form against one-at-a-time on Poisson arrivals.
 """
 
 from __future__ import annotations
@@ -41,15 +47,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 LDS_PEAK_GBS = 128 * 256 * 2.4
 
 
+PROFILES = {"c2": "c2_power_law_hbm_counters.md", "c5": "c5_rmat26_hbm_counters.md"}
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch of the enumeration kernel from the committed counter
-    summary of the power-law workload, or None for another workload or when the
-    kernel source has changed since the counters were taken."""
+    summary of the workload, or None when there is none or the kernel source
+    has changed since the counters were taken."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_2102_10768_amd", "csrc", "enumerate_global.hip")
-    prof = os.path.join(ROOT, "profiles", "c2_power_law_hbm_counters.md")
-    if workload != "c2" or not os.path.exists(prof):
+    prof = os.path.join(ROOT, "profiles", PROFILES.get(workload, "-"))
+    if not os.path.exists(prof):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     vals = {}
@@ -62,52 +71,57 @@ def measured_traffic(workload: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def roofline_of(timed, counted):
-    """Roofline of the dominant enumeration kernel of a plain step.
+def roofline_of(kernel_ms, launches, counted, workload):
+    """Roofline of the enumeration kernel over the timed launches.
 
-    ``timed``: enumeration stats of the timed launches (kernel_ms, launches,
-    mode); ``counted``: (CST info, stats) of the counter pass over the same
-    queries.  Algorithmic bytes per launch: HBM mode reads the CST (S bytes)
-    plus 4 per visited candidate, 4 per non-tree check and 8 per partial
-    result pushed on; LDS mode reads its images from HBM (image bytes) and
-    does the per-candidate work in LDS, reported beside as on-chip bytes
-    against the LDS rate.  Candidates counted by list length carry no bytes."""
-    ms = {}
-    for st in timed:
-        m = 1 if st["mode"] == 1 else 2
-        t = ms.setdefault(m, [0.0, 0])
-        t[0] += st["kernel_ms"]
-        t[1] += st["launches"]
-    mode = max(ms, key=lambda m: ms[m][0]) if ms else 2
-    kern_ms, launches = ms.get(mode, [0.0, 0])
-    rows = [(info, st) for info, st in counted if (1 if st["mode"] == 1 else 2) == mode]
-    N = sum(st["extensions"] for _, st in rows)
-    M = sum(st["edge_checks"] for _, st in rows)
-    F = sum(st["pushed"] for _, st in rows)
-    Nsum = sum(st["summed"] for _, st in rows)
+    ``kernel_ms``: summed duration of the timed launches (HIP events on the
+    launch stream); ``counted``: (CST info, stats) rows of one counter pass
+    over the same launches.  Device-memory mode (k_enumerate_global):
+    algorithmic bytes per launch are the CST (S bytes) plus 4 per visited
+    candidate, 4 per non-tree check and 8 per partial result pushed on;
+    candidates counted by list length carry no bytes.  Those bytes come from
+    L2/MALL far more than from HBM: the measured HBM traffic per launch, when a
+    counter summary for this kernel source exists, is reported beside them
+    (traffic_bytes_per_launch, hbm_gbs).  LDS mode (k_enumerate): the HBM
+    bytes are the staged images; the per-candidate work is priced on chip
+    against the LDS rate."""
+    N = sum(st["extensions"] for _, st in counted)
+    M = sum(st["edge_checks"] for _, st in counted)
+    F = sum(st["pushed"] for _, st in counted)
+    Nsum = sum(st["summed"] for _, st in counted)
+    S = sum(info["bytes"] for info, _ in counted)
+    lds = bool(counted) and all(st["mode"] == 1 for _, st in counted)
+    n_launch = max(1, sum(st["launches"] for _, st in counted))
     work = 4 * (N - Nsum) + 4 * M + 8 * F
-    sec = kern_ms * 1e-3
-    if mode == 2:
-        alg = sum(info["bytes"] for info, _ in rows) + work
+    if lds:
+        alg = sum(st["image_bytes"] for _, st in counted) / n_launch
     else:
-        alg = sum(st["image_bytes"] for _, st in rows)
+        alg = (S + work) / n_launch
+    avg_ms = kernel_ms / max(1, launches)
+    sec = avg_ms * 1e-3
     achieved = alg / sec / 1e9 if sec else 0.0
+    traffic = None if lds else measured_traffic(workload)
     out = {
-        "kernel": "k_enumerate_global" if mode == 2 else "k_enumerate",
+        "kernel": "k_enumerate" if lds else "k_enumerate_global",
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
-        "algorithmic_bytes_per_step": alg,
-        "launches_per_step": launches,
-        "avg_launch_ms": kern_ms / max(1, launches),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_bytes_per_launch": traffic,
+        "hbm_gbs": (traffic / sec / 1e9) if (traffic and sec) else None,
+        "binding_tier": "LDS latency and integer issue" if lds else
+                        "L2/MALL latency (the CST stays on chip; HBM carries a small share of these bytes)",
+        "launches": launches,
+        "avg_launch_ms": avg_ms,
+        "work": {"N": N, "M": M, "F": F, "summed": Nsum, "S": S},
     }
-    if mode == 1:
-        on_chip = work / sec / 1e9 if sec else 0.0
+    if lds:
+        on_chip = work / n_launch / sec / 1e9 if sec else 0.0
         out["on_chip"] = {"achieved": on_chip, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": on_chip / LDS_PEAK_GBS,
-                          "bytes_per_step": work}
+                          "bytes_per_launch": work / n_launch}
     return out
 
 
@@ -117,19 +131,347 @@ def load_workload(name: str):
         return json.load(f)
 
 
+def workload_queries(W, max_queries: int = 0):
+    """(queries, expected counts, per-query limits, INF count) of a stored set;
+    queries the oracle left INF (no stored count) are not run."""
+    from synth import Query
+
+    rows = [d for d in W["queries"] if d.get("count") is not None]
+    inf = len(W["queries"]) - len(rows)
+    if max_queries:
+        rows = rows[:max_queries]
+    lim_all = int(W["workload"]["queries"].get("limit", 0))
+    queries = [Query.from_dict(d) for d in rows]
+    expected = [int(d["count"]) for d in rows]
+    limits = [int(d.get("limit", lim_all) or 0) for d in rows]
+    return queries, expected, limits, inf
+
+
+def say(*x):
+    print(*x, file=sys.stderr, flush=True)
+
+
+class Session:
+    """One workload resident on the device, with the forms the benchmark times."""
+
+    def __init__(self, name: str, mode: str = "auto", build_streams: int = 4, max_queries: int = 0):
+        import torch
+
+        from paper_2102_10768_amd import cstm
+        from synth import make_graph
+
+        self.name = name
+        self.W = load_workload(name)
+        self.queries, self.expected, self.limits, self.inf = workload_queries(self.W, max_queries)
+        say(f"workload {name}: {len(self.queries)} queries ({self.inf} INF at the oracle screen); generating graph")
+        t0 = time.time()
+        self.g = make_graph(self.W["workload"]["graph"], log=say)
+        say(f"graph ready in {time.time() - t0:.1f}s: {self.g.summary()}")
+        self.mode_id = {"auto": 0, "lds": 1, "hbm": 2}[mode]
+        self.ctx = cstm.Context(0, tune={"enum_mode": self.mode_id, "collect_stats": 0})
+        self.stream = torch.cuda.current_stream()
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, build_streams))]
+        g = self.g
+        self.G = cstm.Graph(self.ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
+                            torch.from_numpy(g.label).cuda())
+        torch.cuda.synchronize()
+        self.any_limit = any(self.limits)
+
+    def build_all(self):
+        """Every CST of the workload, built on the session's streams by one host
+        thread each (each build waits for its own stream before returning)."""
+        from concurrent.futures import ThreadPoolExecutor
+
+        from paper_2102_10768_amd import cstm
+
+        S = len(self.streams)
+        out = [None] * len(self.queries)
+
+        def work(t):
+            for i in range(t, len(self.queries), S):
+                q = self.queries[i]
+                out[i] = cstm.CST(self.ctx, self.G, q.qlabel, q.qedges, stream=self.streams[t])
+
+        with ThreadPoolExecutor(S) as ex:
+            list(ex.map(work, range(S)))
+        return out
+
+    def batched_step(self):
+        """All CSTs built, then one persistent launch; returns (counts, stats, build seconds)."""
+        from paper_2102_10768_amd import cstm
+
+        t = time.perf_counter()
+        csts = self.build_all()
+        tb = time.perf_counter() - t
+        try:
+            counts = cstm.batch_count(self.ctx, csts, stream=self.stream,
+                                      limits=self.limits if self.any_limit else None)
+            st = self.ctx.last_enum_stats()
+            infos = [c.info() for c in csts] if self.ctx.tune["collect_stats"] else None
+        finally:
+            for c in csts:
+                c.close()
+        return counts, st, tb, infos
+
+    def plain_step(self, collect=None):
+        """One query per launch: build its CST, count it (with its limit)."""
+        from paper_2102_10768_amd import cstm
+
+        counts = []
+        for q, lim in zip(self.queries, self.limits):
+            c = cstm.CST(self.ctx, self.G, q.qlabel, q.qedges, stream=self.stream)
+            n = c.count(stream=self.stream, limit=lim)
+            counts.append(n)
+            if collect is not None:
+                collect.append((c.info(), self.ctx.last_enum_stats(), c.times()))
+            c.close()
+        return counts
+
+    def bad(self, counts):
+        return [i for i, (x, y) in enumerate(zip(counts, self.expected)) if x != y]
+
+    def close(self):
+        self.G.close()
+        self.ctx.close()
+
+
+def timed(fn, steps: int):
+    import torch
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, outs
+
+
+def autotune_session(S, a):
+    """Launch parameters of the batched form from the autotuner (HBM mode)."""
+    if a.no_autotune:
+        return None
+    from paper_2102_10768_amd import autotune
+
+    tuned = autotune.tune(S.ctx, S.G, S.queries, stream=S.stream, modes=("hbm",), log=say,
+                          limits=S.limits if S.any_limit else None)
+    say(f"autotune chose {tuned['choice']}")
+    return {"choice": tuned["choice"], "calibration": {k: tuned["subset"][k] for k in ("frac", "seed")},
+            "calibration_queries": len(tuned["subset"]["indices"]), "candidates_timed": len(tuned["trials"])}
+
+
+def headline(a):
+    """The batched form of the main workload: the JSON line's value, roofline
+    and CPU baseline, with the plain form on the same queries beside it."""
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries)
+    total = sum(S.expected)
+    bad = []
+    tuned = autotune_session(S, a)
+    # warm-up, with the parity check
+    for _ in range(max(1, a.warmup)):
+        counts, _, _, _ = S.batched_step()
+        bad += [i for i in S.bad(counts) if i not in bad]
+    say(f"warm-up done; {len(bad)} mismatches")
+    steps = []
+    elapsed, outs = timed(lambda: S.batched_step(), a.steps)
+    for counts, st, tb, _ in outs:
+        bad += [i for i in S.bad(counts) if i not in bad]
+        steps.append({"kernel_ms": st["kernel_ms"], "build_s": tb, "launches": st["launches"]})
+    value = total * a.steps / elapsed
+    ms_per_step = 1e3 * elapsed / a.steps
+    say(f"batched: {ms_per_step:.1f} ms/step, {value:.3e} embeddings/s")
+    kernel_ms = sum(x["kernel_ms"] for x in steps)
+    launches = sum(x["launches"] for x in steps)
+    # one counter pass over the same launch (work done, for the roofline)
+    S.ctx.tune = {"collect_stats": 1}
+    counts, st, _, infos = S.batched_step()
+    S.ctx.tune = {"collect_stats": 0}
+    bad += [i for i in S.bad(counts) if i not in bad]
+    roof = roofline_of(kernel_ms, launches, [(dict(bytes=sum(i["bytes"] for i in infos)), st)], a.workload)
+    # the same batched launch visiting every last-level candidate (no list-length sums)
+    S.ctx.tune = {"last_level_sum": -1}
+    tv = time.perf_counter()
+    vcounts, vst, _, _ = S.batched_step()
+    visit_s = time.perf_counter() - tv
+    S.ctx.tune = {"last_level_sum": 1}
+    bad += [i for i in S.bad(vcounts) if i not in bad]
+    # plain form on the same queries, one step
+    per_query = []
+    p_elapsed, pouts = timed(lambda: S.plain_step(per_query), 1)
+    bad += [i for i in S.bad(pouts[0]) if i not in bad]
+    plain_value = total / p_elapsed
+    build_ms = sum(r[2]["build_ms"] for r in per_query)
+    enum_ms = sum(r[2]["enumerate_ms"] for r in per_query)
+    say(f"plain: {1e3 * p_elapsed:.1f} ms/step, {plain_value:.3e} embeddings/s")
+    gs = S.W["graph_summary"]
+    out = {
+        "metric": "embeddings/sec",
+        "value": value,
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": S.W["workload"]["title"],
+            "name": a.workload,
+            "queries": len(S.queries),
+            "queries_inf_at_oracle_screen": S.inf,
+            "result_limit_per_query": max(S.limits) if S.any_limit else 0,
+            "embeddings_per_step": total,
+            "form": f"batched: every CST built ({len(S.streams)} build streams), then one persistent launch "
+                    "over a device task queue",
+            "enum_mode": a.mode,
+            "graph": {k: gs[k] for k in ("n", "m", "max_degree") if k in gs},
+        },
+        "parity": {"checked": len(S.expected), "mismatches": len(bad), "runs_checked": a.warmup + a.steps + 3},
+        "stages_ms_per_step": {
+            "cst_builds_wall": 1e3 * sum(x["build_s"] for x in steps) / len(steps),
+            "enumeration_kernel": kernel_ms / len(steps),
+        },
+        "plain": {
+            "value": plain_value,
+            "ms_per_step": 1e3 * p_elapsed,
+            "form": "one query per launch: build its CST, count it",
+            "stages_ms_per_step": {"cst_build": build_ms, "enumerate": enum_ms},
+            "batched_vs_plain": value / plain_value if plain_value else None,
+        },
+        "last_level_sum": {
+            "summed_fraction_of_N": roof["work"]["summed"] / roof["work"]["N"] if roof["work"]["N"] else 0.0,
+            "value_visiting_every_candidate": total / visit_s,
+            "visiting_kernel_ms": vst["kernel_ms"],
+        },
+        "autotune": tuned,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"], out["cpu_baseline_1thread"] = cpu_baselines(S, a)
+    S.close()
+    if bad:
+        say(f"COUNT MISMATCH {a.workload}: queries {bad}")
+    return out, bad
+
+
+def cpu_baselines(S, a):
+    """The oracle (all host cores, then one thread) on a bounded sample of the
+    same workload: whole queries with their limits, in stored order, until
+    about a.cpu_seconds (a.cpu_seconds / 2 for the one-thread run)."""
+    import oracle
+
+    t = time.time()
+    lcol = oracle.label_grouped_col(S.g)  # the oracle's label-grouped rows, prepared outside the sample
+    say(f"oracle rows regrouped in {time.time() - t:.1f}s")
+
+    def sample(threads, budget_s):
+        """Whole queries in stored order until the budget is spent; the query
+        the budget ends in counts with what the oracle found by then."""
+        done, found, spent, used, partial = 0, 0, 0.0, 0, False
+        for q, lim, want in zip(S.queries, S.limits, S.expected):
+            if spent >= budget_s:
+                break
+            t = time.time()
+            r = oracle.match(S.g, q, lcol=lcol, limit=lim, threads=threads, deadline_s=max(1.0, budget_s - spent))
+            spent += time.time() - t
+            used = r.threads
+            found += r.count
+            if r.status != oracle.OK:
+                partial = True
+                break
+            if r.count != want:
+                raise SystemExit(f"oracle disagrees with the stored count on a query: {r.count} != {want}")
+            done += 1
+        return found, spent, done, used, partial
+
+    out = []
+    for threads, budget in ((0, a.cpu_seconds), (1, a.cpu_seconds / 2)):
+        found, spent, done, used, partial = sample(threads, budget)
+        say(f"oracle ({used} threads): {done} whole queries, {found} embeddings in {spent:.1f}s")
+        out.append({
+            "value": found / spent if spent else 0.0,
+            "unit": "embeddings/s",
+            "cores": used,
+            "kind": "oracle",
+            "sample": f"oracle (label-grouped rows, {used} threads) on the same workload's queries in stored order, "
+                      f"each to its stored count (limits as stored), for {spent:.1f}s: {done} whole queries"
+                      + (" and part of the next" if partial else "") + f", {found} embeddings",
+            "cpu_model": cpu_model(),
+            "nproc": os.cpu_count(),
+        })
+    return out[0], out[1]
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def extra_workload(a, name):
+    """Plain and batched forms of another stored workload (and, for the
+    power-law one, a short served-vs-plain comparison)."""
+    S = Session(name, a.mode, a.build_streams)
+    total = sum(S.expected)
+    bad = []
+    counts = S.plain_step()
+    bad += S.bad(counts)
+    per_query = []
+    p_elapsed, pouts = timed(lambda: S.plain_step(per_query), 1)
+    bad += [i for i in S.bad(pouts[0]) if i not in bad]
+    tuned = autotune_session(S, a)
+    counts, _, _, _ = S.batched_step()
+    bad += [i for i in S.bad(counts) if i not in bad]
+    b_elapsed, bouts = timed(lambda: S.batched_step(), max(1, a.steps))
+    for counts, _, _, _ in bouts:
+        bad += [i for i in S.bad(counts) if i not in bad]
+    bsteps = max(1, a.steps)
+    row = {
+        "workload": S.W["workload"]["title"],
+        "queries": len(S.queries),
+        "embeddings_per_step": total,
+        "plain": {"value": total / p_elapsed, "ms_per_step": 1e3 * p_elapsed,
+                  "stages_ms_per_step": {"cst_build": sum(r[2]["build_ms"] for r in per_query),
+                                         "enumerate": sum(r[2]["enumerate_ms"] for r in per_query)}},
+        "batched": {"value": total * bsteps / b_elapsed, "ms_per_step": 1e3 * b_elapsed / bsteps,
+                    "kernel_ms": sum(o[1]["kernel_ms"] for o in bouts) / bsteps, "autotune": tuned},
+        "parity": {"checked": len(S.expected), "mismatches": len(bad)},
+    }
+    row["batched"]["vs_plain"] = row["batched"]["value"] / row["plain"]["value"]
+    if name == "c2" and a.served_requests > 0:
+        S.ctx.tune = {"hbm_wgs_per_cu": 0, "hbm_donate_min": 0, "hbm_donate_period": 0, "hbm_flat_max": 0,
+                      "hbm_donate_last_min": 0, "enum_mode": S.mode_id}
+        srow, bad_s = served_vs_plain(S.ctx, S.G, S.queries, S.expected, a.served_requests, a.served_qps, 201)
+        row["served"] = {"form": "cstm_server (2 builders, 2 lanes, batching window 2 ms) vs one at a time, "
+                                 "same Poisson arrivals", **srow}
+        row["parity"]["checked"] += 2 * a.served_requests
+        row["parity"]["mismatches"] += bad_s
+        bad += ["served"] * bad_s
+    say(f"{name}: plain {row['plain']['value']:.3e}, batched {row['batched']['value']:.3e} embeddings/s")
+    S.close()
+    return row, bad
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--extras", default="c2,c3", help="other stored workloads reported beside the main one")
     ap.add_argument("--mode", default="auto", choices=["auto", "hbm", "lds"])
+    ap.add_argument("--build-streams", type=int, default=4, help="streams (host threads) building CSTs in parallel")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the default launch parameters")
     ap.add_argument("--served-requests", type=int, default=120,
-                    help="requests in the short served-vs-plain comparison of the default run (0: skip)")
+                    help="requests in the short served-vs-plain comparison on the power-law workload (0: skip)")
     ap.add_argument("--served-qps", type=float, default=25.0, help="arrival rate of that comparison")
     ap.add_argument("--serve", action="store_true",
                     help="request-serving form: Poisson arrivals, served loop vs one-at-a-time, p50/p99 latency")
@@ -149,201 +491,33 @@ def main():
               f"in the design notes and is not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
+    if a.serve or a.share or a.orders:
+        from synth import make_graph
 
-    from paper_2102_10768_amd import cstm
-    from synth import Query, make_graph
-
-    W = load_workload(a.workload)
-    queries = [Query.from_dict(d) for d in W["queries"]]
-    expected = [int(d["count"]) for d in W["queries"]]
-    if a.max_queries:
-        queries, expected = queries[: a.max_queries], expected[: a.max_queries]
-    print(f"workload {a.workload}: {len(queries)} queries; generating graph", file=sys.stderr, flush=True)
-    t0 = time.time()
-    g = make_graph(W["workload"]["graph"], log=lambda m: print(m, file=sys.stderr, flush=True))
-    print(f"graph ready in {time.time() - t0:.1f}s: {g.summary()}", file=sys.stderr, flush=True)
-
-    if a.serve:
-        return serve_main(a, W, g, queries, expected)
-    if a.share:
-        return share_main(a, W, g, queries, expected)
-    if a.orders:
+        W = load_workload(a.workload)
+        queries, expected, _, _ = workload_queries(W, a.max_queries)
+        t0 = time.time()
+        g = make_graph(W["workload"]["graph"], log=say)
+        say(f"graph ready in {time.time() - t0:.1f}s: {g.summary()}")
+        if a.serve:
+            return serve_main(a, W, g, queries, expected)
+        if a.share:
+            return share_main(a, W, g, queries, expected)
         return orders_main(a, W, g, queries, expected)
 
-    mode_id = {"auto": 0, "lds": 1, "hbm": 2}[a.mode]
-    ctx = cstm.Context(0, tune={"enum_mode": mode_id, "collect_stats": 0})
-    stream = torch.cuda.current_stream()
-    G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
-                   torch.from_numpy(g.label).cuda())
-    torch.cuda.synchronize()
-    l2_budget = 4 << 20  # one XCD's L2: the on-chip tier the HBM mode keeps each CST in
-    cst_bytes = []
-
-    def plain_step(collect=None):
-        total = 0
-        counts = []
-        for q in queries:
-            c = cstm.CST(ctx, G, q.qlabel, q.qedges, stream=stream)
-            info = c.info()
-            # Algorithm 2 at the L2 budget: a CST within it needs no split in HBM mode
-            cst_bytes.append(info["bytes"])
-            n = c.count(stream=stream)
-            counts.append(n)
-            total += n
-            if collect is not None:
-                st = ctx.last_enum_stats()
-                t = c.times()
-                collect.append((info, st, t))
-            c.close()
-        return total, counts
-
-    def batched_step():
-        csts = [cstm.CST(ctx, G, q.qlabel, q.qedges, stream=stream) for q in queries]
-        counts = cstm.batch_count(ctx, csts, stream=stream)
-        st = ctx.last_enum_stats()
-        for c in csts:
-            c.close()
-        return sum(counts), counts, st
-
-    # warm-up, with the parity check
-    for _ in range(max(1, a.warmup)):
-        _, counts = plain_step()
-    bad = [i for i, (x, y) in enumerate(zip(counts, expected)) if x != y]
-
-    # timed plain steps
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    per_query = []
-    for s in range(a.steps):
-        total, _ = plain_step(per_query if s == 0 else None)
-        print(f"step {s} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = 1e3 * elapsed / a.steps
-    value = total * a.steps / elapsed
-
-    # enumeration-kernel roofline: one stats pass (counters on), timing from the timed steps
-    ctx.tune = {"collect_stats": 1}
-    stats_rows = []
-    plain_step(stats_rows)
-    ctx.tune = {"collect_stats": 0}
-
-    # the same plain step visiting every last-level candidate (no list-length sums)
-    visit_value = None
-    if mode_id != 1:
-        ctx.tune = {"last_level_sum": -1}
-        torch.cuda.synchronize()
-        tv = time.perf_counter()
-        vtotal, vcounts = plain_step()
-        torch.cuda.synchronize()
-        visit_value = vtotal / (time.perf_counter() - tv)
-        ctx.tune = {"last_level_sum": 1}
-        bad += [i for i, (x, y) in enumerate(zip(vcounts, expected)) if x != y and i not in bad]
-
-    # batched form on the same queries, launch parameters from the autotuner
-    tuned = None
-    if not a.no_autotune:
-        from paper_2102_10768_amd import autotune
-
-        tuned = autotune.tune(ctx, G, queries, stream=stream,
-                              log=lambda m: print(m, file=sys.stderr, flush=True))
-        print(f"autotune chose {tuned['choice']}", file=sys.stderr, flush=True)
-    btotal, bcounts, _ = batched_step()
-    bad_b = [i for i, (x, y) in enumerate(zip(bcounts, expected)) if x != y]
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    bsteps = max(1, a.steps)
-    for _ in range(bsteps):
-        btotal, _, bst = batched_step()
-    torch.cuda.synchronize()
-    b_elapsed = time.perf_counter() - tb
-
-    roof = roofline_of([r[1] for r in per_query], [(r[0], r[1]) for r in stats_rows])
-    N = sum(r[1]["extensions"] for r in stats_rows)
-    Nsum = sum(r[1]["summed"] for r in stats_rows)
-    build_ms = sum(r[2]["build_ms"] for r in per_query)
-    enum_ms = sum(r[2]["enumerate_ms"] for r in per_query)
-
-    out = {
-        "metric": "embeddings/sec",
-        "value": value,
-        "unit": "embeddings/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": W["workload"]["title"],
-            "name": a.workload,
-            "queries": len(queries),
-            "embeddings_per_step": total,
-            "form": "plain: one query per launch (build CST, check partition budget, count)",
-            "enum_mode": a.mode,
-            "graph": {k: W["graph_summary"][k] for k in ("n", "m", "max_degree") if k in W["graph_summary"]},
-            "max_cst_bytes": max(cst_bytes) if cst_bytes else 0,
-            "csts_within_l2_budget": sum(b <= l2_budget for b in cst_bytes[: len(queries)]),
-        },
-        "parity": {"checked": len(expected), "mismatches": len(bad) + len(bad_b)},
-        "stages_ms_per_step": {"cst_build": build_ms, "enumerate": enum_ms},
-        "last_level_sum": {
-            "summed_fraction_of_N": Nsum / N if N else 0.0,
-            "value_visiting_every_candidate": visit_value,
-            "note": "value counts an unconstrained last level by list lengths; the visiting form is one "
-                    "untimed-warm plain step with every last-level candidate read",
-        },
-        "batched": {
-            "value": btotal * bsteps / b_elapsed,
-            "ms_per_step": 1e3 * b_elapsed / bsteps,
-            "kernel_ms": bst["kernel_ms"],
-            "form": "all CSTs built, then one persistent launch over a device task queue",
-            "vs_plain": (btotal * bsteps / b_elapsed) / value if value else None,
-            "autotune": None if tuned is None else {
-                "choice": tuned["choice"], "calibration": {k: tuned["subset"][k] for k in ("frac", "seed")},
-                "calibration_queries": len(tuned["subset"]["indices"]), "candidates_timed": len(tuned["trials"])},
-        },
-        "roofline": roof,
-    }
-    if roof["kernel"] == "k_enumerate_global":
-        roof["traffic"] = measured_traffic(a.workload)
-    # served form on the same pool: a short Poisson stream through the library's
-    # server and through the one-at-a-time form (p50/p99 latency, throughput)
-    if a.served_requests > 0:
-        ctx.tune = {"hbm_wgs_per_cu": 0, "hbm_donate_min": 0, "hbm_donate_period": 0, "hbm_flat_max": 0,
-                    "hbm_donate_last_min": 0, "enum_mode": mode_id}
-        row, bad_s = served_vs_plain(ctx, G, queries, expected, a.served_requests, a.served_qps, 201)
-        out["served"] = {"form": "cstm_server (2 builders, 2 lanes, batching window 2 ms) vs one at a time, "
-                                 "same Poisson arrivals", **row}
-        out["parity"]["checked"] += 2 * a.served_requests
-        out["parity"]["mismatches"] += bad_s
-        bad = bad + ["served"] * bad_s
-        print(f"served: p50 {row['served']['p50_ms']:.1f} ms vs plain {row['plain']['p50_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
-    if not a.no_cpu_baseline:
-        import oracle
-
-        q0 = queries[0]
-        lcol = oracle.label_grouped_col(g)  # the oracle's label-grouped rows, prepared outside the sample
-        t = time.time()
-        r = oracle.match(g, q0, deadline_s=a.cpu_seconds, lcol=lcol)
-        dt = time.time() - t
-        out["cpu_baseline"] = {
-            "value": r.count / dt,
-            "unit": "embeddings/s",
-            "cores": r.threads,
-            "kind": "oracle",
-            "sample": f"oracle (label-grouped rows) on query 0 for {dt:.1f}s: {r.count} of {expected[0]} "
-                      f"embeddings ({'finished' if r.status == 0 else 'stopped at the time limit'})",
-        }
-    print(json.dumps(out), flush=True)
-    if bad or bad_b:
-        print(f"COUNT MISMATCH plain {bad} batched {bad_b}", file=sys.stderr)
+    out, bad = headline(a)
+    extras = {}
+    for name in [x for x in a.extras.split(",") if x and x != a.workload]:
+        row, bad_x = extra_workload(a, name)
+        extras[name] = row
+        out["parity"]["checked"] += row["parity"]["checked"]
+        out["parity"]["mismatches"] += row["parity"]["mismatches"]
+        bad += [f"{name}:{i}" for i in bad_x]
+    if extras:
+        out["extra_workloads"] = extras
+    print(json.dumps(out, default=float), flush=True)
+    if bad:
+        print(f"COUNT MISMATCH {bad}", file=sys.stderr)
         sys.exit(1)
 
 

@@ -53,17 +53,17 @@ def calibration_subset(n: int, frac: float = 0.05, seed: int = 301, min_n: int =
     return sorted(int(i) for i in rng.choice(n, size=m, replace=False))
 
 
-def _time_setting(ctx, graph, queries, setting: dict, repeats: int, stream):
+def _time_setting(ctx, graph, queries, setting: dict, repeats: int, stream, limits=None):
     """Fresh CSTs (an LDS setting partitions them on its first launch), one
     untimed launch, then ``repeats`` timed launches; returns (best seconds, counts)."""
     ctx.tune = setting
     csts = [cstm.CST(ctx, graph, q.qlabel, q.qedges, stream=stream) for q in queries]
     try:
-        counts = cstm.batch_count(ctx, csts, stream=stream)
+        counts = cstm.batch_count(ctx, csts, stream=stream, limits=limits)
         best = float("inf")
         for _ in range(repeats):
             t = time.perf_counter()
-            got = cstm.batch_count(ctx, csts, stream=stream)
+            got = cstm.batch_count(ctx, csts, stream=stream, limits=limits)
             best = min(best, time.perf_counter() - t)
             if got != counts:
                 raise RuntimeError("counts changed between launches of one setting")
@@ -74,13 +74,15 @@ def _time_setting(ctx, graph, queries, setting: dict, repeats: int, stream):
 
 
 def tune(ctx, graph, queries, *, frac: float = 0.05, seed: int = 301, repeats: int = 2,
-         modes=("hbm", "lds"), stream=None, log=None) -> dict:
+         modes=("hbm", "lds"), stream=None, log=None, limits=None) -> dict:
     """Choose launch parameters for ``batch_count`` over ``queries`` (see the module docstring).
 
-    ``queries`` are objects with ``qlabel`` and ``qedges``.  Returns a record
-    with the chosen setting, the subset used and every timing."""
+    ``queries`` are objects with ``qlabel`` and ``qedges``; ``limits`` (optional,
+    one per query) are the per-query result limits of the batch.  Returns a
+    record with the chosen setting, the subset used and every timing."""
     idx = calibration_subset(len(queries), frac, seed)
     sub = [queries[i] for i in idx]
+    sub_limits = None if limits is None else [int(limits[i]) for i in idx]
     base = dict(ctx.tune)
     base["collect_stats"] = 0
     trials = []
@@ -92,7 +94,7 @@ def tune(ctx, graph, queries, *, frac: float = 0.05, seed: int = 301, repeats: i
         if best_sec < float("inf"):
             full["deadline_ms"] = max(100, int(4e3 * best_sec) + 1)
         try:
-            sec, counts = _time_setting(ctx, graph, sub, full, repeats, stream)
+            sec, counts = _time_setting(ctx, graph, sub, full, repeats, stream, sub_limits)
         except cstm.CstmError as e:
             why = "slower than the deadline" if e.status == cstm.ETIMEOUT else str(e)
             trials.append({"setting": setting, "error": why})

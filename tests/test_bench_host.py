@@ -51,29 +51,39 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path):
     assert b.measured_traffic("c2") is None
 
 
-def _st(mode, ms, N=0, M=0, F=0, summed=0, image_bytes=0):
-    return {"mode": mode, "kernel_ms": ms, "launches": 1, "extensions": N, "edge_checks": M, "pushed": F,
+def _st(mode, ms, N=0, M=0, F=0, summed=0, image_bytes=0, launches=1):
+    return {"mode": mode, "kernel_ms": ms, "launches": launches, "extensions": N, "edge_checks": M, "pushed": F,
             "summed": summed, "image_bytes": image_bytes}
 
 
-def test_roofline_prices_the_dominant_kernel():
+def test_roofline_prices_the_enumeration_kernel():
     b = _bench()
-    # device-memory mode only: CST bytes + 4 per read candidate + 4 per check + 8 per push
-    timed = [_st(2, 10.0), _st(2, 30.0)]
+    # device-memory mode: CST bytes + 4 per read candidate + 4 per check + 8 per push, per launch
     counted = [({"bytes": 1000}, _st(2, 0, N=100, M=10, F=5, summed=40)),
                ({"bytes": 3000}, _st(2, 0, N=50, M=0, F=1))]
-    r = b.roofline_of(timed, counted)
-    alg = 1000 + 3000 + 4 * (150 - 40) + 4 * 10 + 8 * 6
-    assert r["kernel"] == "k_enumerate_global" and r["algorithmic_bytes_per_step"] == alg
-    assert abs(r["achieved"] - alg / 0.040 / 1e9) < 1e-12
-    assert r["launches_per_step"] == 2 and abs(r["avg_launch_ms"] - 20.0) < 1e-12
+    r = b.roofline_of(40.0, 2, counted, "c3")
+    alg = (1000 + 3000 + 4 * (150 - 40) + 4 * 10 + 8 * 6) / 2
+    assert r["kernel"] == "k_enumerate_global" and r["algorithmic_bytes_per_launch"] == alg
+    assert abs(r["avg_launch_ms"] - 20.0) < 1e-12
+    assert abs(r["achieved"] - alg / 0.020 / 1e9) < 1e-12
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15 and "on_chip" not in r
-    # LDS images dominate: HBM bytes are the images, the list work is on chip
-    timed = [_st(1, 50.0), _st(2, 5.0)]
-    counted = [({"bytes": 1000}, _st(1, 0, N=100, M=10, F=5, image_bytes=7000)),
-               ({"bytes": 3000}, _st(2, 0, N=50))]
-    r = b.roofline_of(timed, counted)
-    assert r["kernel"] == "k_enumerate" and r["algorithmic_bytes_per_step"] == 7000
-    assert r["on_chip"]["bytes_per_step"] == 4 * 100 + 4 * 10 + 8 * 5
+    assert r["traffic"] is None and r["hbm_gbs"] is None  # no counter summary for this workload
+    # LDS images: HBM bytes are the images, the list work is on chip
+    counted = [({"bytes": 1000}, _st(1, 0, N=100, M=10, F=5, image_bytes=7000))]
+    r = b.roofline_of(50.0, 1, counted, "c3")
+    assert r["kernel"] == "k_enumerate" and r["algorithmic_bytes_per_launch"] == 7000
+    assert r["on_chip"]["bytes_per_launch"] == 4 * 100 + 4 * 10 + 8 * 5
     assert abs(r["on_chip"]["peak"] - 128 * 256 * 2.4) < 1e-9
-    assert b.roofline_of([], [])["achieved"] == 0.0
+    assert b.roofline_of(0.0, 0, [], "c3")["achieved"] == 0.0
+
+
+def test_workload_queries_skip_inf_and_carry_limits():
+    b = _bench()
+    W = {"workload": {"queries": {"limit": 7}},
+         "queries": [{"qlabel": [0, 1], "qedges": [[0, 1]], "count": 3, "limit": 7},
+                     {"qlabel": [0, 1], "qedges": [[0, 1]], "count": None, "limit": 7},
+                     {"qlabel": [2], "qedges": [], "count": 5}]}
+    qs, exp, lim, inf = b.workload_queries(W)
+    assert exp == [3, 5] and lim == [7, 7] and inf == 1 and [q.k for q in qs] == [2, 1]
+    qs, exp, lim, inf = b.workload_queries(W, max_queries=1)
+    assert exp == [3] and inf == 1
