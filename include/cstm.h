@@ -116,7 +116,15 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      which idle wavefronts see neither a task nor a beat for
  *                      this many milliseconds stops with CSTM_EDEVICE
  *                      (default 30000).  A deadline that passes first is
- *                      reported as CSTM_ETIMEOUT.                            */
+ *                      reported as CSTM_ETIMEOUT.
+ *   order_rule         matching order of cstm_cst_build: 0 (default) the
+ *                      path-based order of Section V-B (root-to-leaf paths
+ *                      by their number of CST path embeddings); 1 constraint
+ *                      first: after the root, repeatedly the vertex whose tree
+ *                      parent is placed with the most placed query neighbours
+ *                      (then the larger query degree, then the smaller id),
+ *                      so that non-tree edges are checked early.  Any such
+ *                      order gives the same embeddings (Section VII-C).     */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -137,6 +145,7 @@ typedef struct {
     int32_t hbm_donate_min;
     int32_t batch_order;
     int32_t hbm_idle_ms;
+    int32_t order_rule;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).
@@ -150,7 +159,10 @@ typedef struct {
  *   edge_checks    M: non-tree edge validations executed;
  *   pushed         F: surviving partial results that were extended further;
  *   summed         last-level extensions counted by list length, not
- *                  visited (tune.last_level_sum; included in extensions).
+ *                  visited (tune.last_level_sum; included in extensions);
+ *   chunks         HBM mode: 64-lane rounds that read candidates, so
+ *                  (extensions - summed) / (64 * chunks) is the share of
+ *                  lanes that held a candidate.
  * The work counters are zero unless tune.collect_stats was set. */
 typedef struct {
     double kernel_ms;
@@ -163,6 +175,7 @@ typedef struct {
     uint64_t pushed;
     double busy_frac;    /* HBM mode: share of wavefront time spent expanding  */
     uint64_t summed;
+    uint64_t chunks;
 } cstm_enum_stats;
 
 /* Facts about a built (and possibly partitioned) CST, for reports and tests. */

@@ -5,6 +5,8 @@ fast that launch runs depends on knobs that leave every count unchanged:
 
 * where the CST is read from and how it is cut (``enum_mode``; in LDS mode the
   partition budget delta_S of Section V-B follows from ``wgs_per_cu``),
+* the matching order the CSTs are built with (``order_rule``: the path-based
+  order of Section V-B, or non-tree constraints first),
 * how many wavefronts share a task (``waves_per_wg``, ``hbm_wgs_per_cu``),
 * how often and how deep work is handed to idle wavefronts
   (``hbm_donate_period``, ``hbm_donate_last_min``) and from what frontier
@@ -30,6 +32,7 @@ from . import cstm
 
 # knob -> values tried, per enumeration mode
 HBM_KNOBS = {
+    "order_rule": [0, 1],
     "hbm_wgs_per_cu": [2, 3, 4],
     "hbm_donate_min": [4, 16, 32],
     "hbm_donate_period": [64, 256],

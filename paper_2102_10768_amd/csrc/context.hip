@@ -150,6 +150,7 @@ static void apply_defaults(cstm_ctx* c) {
     if (t.last_level_sum == 0) t.last_level_sum = 1;
     if (t.hbm_donate_min <= 0) t.hbm_donate_min = 16;
     if (t.hbm_idle_ms <= 0) t.hbm_idle_ms = 30000;
+    if (t.order_rule < 0 || t.order_rule > 1) t.order_rule = 0;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,

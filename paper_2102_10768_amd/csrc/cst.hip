@@ -695,6 +695,27 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             c->order[i] = u;
         }
         for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
+    } else if (c->ctx->tune.order_rule == 1) {
+        // constraint first: among the vertices whose tree parent is placed,
+        // the one with the most placed query neighbours (so non-tree edges
+        // are checked as early as the tree allows), then the larger query
+        // degree, then the smaller id
+        uint32_t placed = 1u << root;
+        c->order[0] = root;
+        for (int i = 1; i < k; ++i) {
+            int best = -1, best_nb = -1;
+            for (int u = 0; u < k; ++u) {
+                if ((placed >> u & 1u) || !(placed >> c->parent[u] & 1u)) continue;
+                const int nb = __builtin_popcount(q.adj[u] & placed);
+                if (nb > best_nb || (nb == best_nb && c->qdeg[u] > c->qdeg[best])) {
+                    best = u;
+                    best_nb = nb;
+                }
+            }
+            placed |= 1u << best;
+            c->order[i] = best;
+        }
+        for (int i = 0; i < k; ++i) c->pos_of[c->order[i]] = i;
     } else {
         // root-to-leaf paths and their numbers of CST path embeddings, all
         // computed before one wait

@@ -67,7 +67,7 @@ struct GArgs {
     int32_t* rows;
     uint64_t cap;
     unsigned long long* row_cursor;
-    unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks, summed] or nullptr
+    unsigned long long* stats;  // [tasks, donated, N, M, F, wait ticks, busy ticks, summed, chunks] or nullptr
     uint64_t idle_limit;        // s_memrealtime ticks (100 MHz) an idle wave waits while no wave makes progress
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
     int donate_period;          // longest interval in chunks between donation checks (<= 0: never donate)
@@ -238,16 +238,62 @@ __device__ long long pop_task(const GArgs& A, int lane) {
     return __shfl(slot, 0);
 }
 
-// Combined length of the last-level lists of the survivors (lanes with ok) at level d = k-2.
-__device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, bool ok, int32_t v, int32_t pl, int lane,
-                                     int32_t my_par, const int64_t* my_toff) {
-    const int L = d + 1;
-    const int pk = rl(my_par, L);
-    const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
+// Membership of data vertex x in a tree list: its entries are indices into
+// the candidate array gid, in ascending data-vertex order.
+__device__ inline bool in_tree_list(const int32_t* tadj, const int32_t* gid, int64_t lo, int64_t hi, int32_t x) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t y = gid[tadj[mid]];
+        if (y == x) return true;
+        if (y < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return false;
+}
+
+// The candidates of level L for a partial result whose level-d entry is v
+// (d = L - 1) and whose earlier levels are in pl must lie in every list that
+// ends at L: the tree list of its parent's candidate and the non-tree list of
+// each earlier neighbour's candidate.  The shortest of them is the one read
+// (ties keep the tree list); every other list becomes a check.  Returns the
+// non-tree edge index of that list, or -1 for the tree list, and its range.
+// Only the partial result decides, so a task handed to another wavefront
+// picks the same list again.
+__device__ inline int pick_list(const CstDev* D, int L, int d, int32_t v, int32_t pl, int32_t my_par,
+                                const int64_t* my_toff, uint32_t my_nt, uint32_t my_ntf, int64_t& lo, int64_t& hi) {
+    const int p = rl(my_par, L);
+    const int64_t* toff = (const int64_t*)rlp(my_toff, L);
+    const int32_t x = p == d ? v : rl(pl, p);
+    lo = toff[x];
+    hi = toff[x + 1];
+    int src = -1;
+    uint32_t ntm = rl(my_nt, L);
+    uint32_t e = rl(my_ntf, L);
+    while (ntm) {
+        const int jj = __ffs(ntm) - 1;
+        ntm &= ntm - 1;
+        const NtDesc& N = D->nt[e];
+        const int32_t xa = jj == d ? v : rl(pl, jj);
+        const int64_t a = N.off[xa], b = N.off[xa + 1];
+        if (b - a < hi - lo) {
+            lo = a;
+            hi = b;
+            src = (int)e;
+        }
+        ++e;
+    }
+    return src;
+}
+
+// Combined length of the level d+1 lists the survivors (lanes with ok) of a
+// level-d chunk would read.
+__device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, bool ok, int32_t v, int32_t pl,
+                                     int32_t my_par, const int64_t* my_toff, uint32_t my_nt, uint32_t my_ntf) {
     int64_t len = 0;
     if (ok) {
-        const int32_t x = pk == d ? v : rl(pl, pk);
-        len = toffL[x + 1] - toffL[x];
+        int64_t lo, hi;
+        pick_list(D, d + 1, d, v, pl, my_par, my_toff, my_nt, my_ntf, lo, hi);
+        len = hi - lo;
     }
     return wave_sum(len, A.small_lists);
 }
@@ -264,7 +310,8 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
                                                 const int64_t* my_toff, const int32_t* my_tadj,
                                                 const int32_t* my_gid, uint32_t my_need, uint32_t my_same,
                                                 uint32_t my_nt, uint32_t my_ntf, uint32_t my_u, bool sum_next,
-                                                uint64_t& cnt, uint64_t& nN, uint64_t& nM, uint64_t& nS) {
+                                                uint64_t& cnt, uint64_t& nN, uint64_t& nM, uint64_t& nS,
+                                                uint64_t& nC) {
     const int L = d + 1;
     const int pk = rl(my_par, L);
     const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
@@ -277,10 +324,11 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
     const int64_t* toffK = sum_next ? (const int64_t*)rlp(my_toff, L + 1) : nullptr;
     int64_t b0 = 0;
     int32_t len = 0;  // the caller checked that the lengths sum to at most flat_max < 2^31
+    int src = -1;     // the list each survivor reads (pick_list)
     if (ok) {
-        const int32_t x = pk == d ? v : rl(pl, pk);
-        b0 = toffL[x];
-        len = (int32_t)(toffL[x + 1] - b0);
+        int64_t hi = 0;
+        src = pick_list(D, L, d, v, pl, my_par, my_toff, my_nt, my_ntf, b0, hi);
+        len = (int32_t)(hi - b0);
     }
     const int32_t incl = wave_incl_add(len);  // inclusive prefix over lanes
     const int32_t total = __builtin_amdgcn_readlane(incl, CSTM_WAVE - 1);
@@ -311,7 +359,8 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
             carry = __builtin_amdgcn_readlane(own[r], CSTM_WAVE - 1);
         }
         bool val2[R], ok2[R];
-        int32_t v2[R], g2[R], vs[R], gs[R];
+        int32_t v2[R], g2[R], vs[R], gs[R], sr[R];
+        int64_t at[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int sl = own[r];
@@ -320,10 +369,13 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
             const int64_t bs = __shfl(b0, sl);
             vs[r] = __shfl(v, sl);
             gs[r] = __shfl(g, sl);
-            v2[r] = val2[r] ? tadjL[bs + (t[r] - start)] : 0;
+            sr[r] = __shfl(src, sl);
+            at[r] = bs + (t[r] - start);
+            v2[r] = val2[r] ? (sr[r] < 0 ? tadjL[at[r]] : D->nt[sr[r]].adj[at[r]]) : 0;
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) g2[r] = (val2[r] && needL) ? gidL[v2[r]] : -1;
+        for (int r = 0; r < R; ++r)
+            g2[r] = (val2[r] && needL) ? (sr[r] < 0 ? gidL[v2[r]] : D->nt[sr[r]].adj_gid[at[r]]) : -1;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             bool okr = val2[r];
@@ -337,9 +389,16 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
             while (nt2) {
                 const int jj = __ffs(nt2) - 1;
                 nt2 &= nt2 - 1;
-                const NtDesc& N = D->nt[e2++];
+                const int ei = (int)e2++;
+                if (ei == sr[r]) continue;  // the list this candidate came from
+                const NtDesc& N = D->nt[ei];
                 const int32_t x = jj == d ? vs[r] : rl(pl, jj);
                 if (okr) okr = contains(N.adj_gid, N.off[x], N.off[x + 1], g2[r]);
+            }
+            if (okr && sr[r] >= 0) {
+                // read from a non-tree list: the tree edge is the check
+                const int32_t xp = pk == d ? vs[r] : rl(pl, pk);
+                okr = in_tree_list(tadjL, gidL, toffL[xp], toffL[xp + 1], g2[r]);
             }
             ok2[r] = okr;
         }
@@ -362,6 +421,7 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
             const uint64_t m2 = __ballot(ok2[r]);
             const uint64_t nv2 = (uint64_t)__popcll(__ballot(val2[r]));
             nN += nv2;
+            nC += nv2 ? 1 : 0;
             nM += nv2 * (uint64_t)__popc(ntL);
             passed += (uint64_t)__popcll(m2);
             if (sum_next) continue;
@@ -396,7 +456,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0, my_need = 0;
     bool sum_last = false;  // this query's last level is counted by list lengths
     const CstDev* D = nullptr;
-    uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, ntasks = 0, ndon = 0;
+    uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, nC = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
     uint64_t my_beat = 0;  // lane 0: when this wavefront last refreshed the progress beat
     // chunks between checks for waiting consumers, adapted per wavefront
@@ -451,8 +511,15 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
         if (lane < j && my_need) pg = my_gid[pl];
         int64_t lc = 0, le = 0;
         uint64_t lm = 0;
+        int32_t ls = -1;  // lane d: the list level d reads (-1: tree list, else a non-tree edge)
         lc = setl(lc, lo, lane, j);
         le = setl(le, hi, lane, j);
+        if (j > 0) {
+            // the task's range lies in the list its prefix picks
+            int64_t a, b;
+            const int src = pick_list(D, j, j - 1, rl(pl, j - 1), pl, my_par, my_toff, my_nt, my_ntf, a, b);
+            ls = setl(ls, (int32_t)src, lane, j);
+        }
         int d = j;
         uint32_t since_check = 0;
         for (;;) {
@@ -477,9 +544,11 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 const int64_t idx = cur + lane;
                 const bool val = idx < end;
                 const int32_t* gid = (const int32_t*)rlp(my_gid, d);
+                const int32_t* tadj = (const int32_t*)rlp(my_tadj, d);
+                const int src = d == 0 ? -1 : rl(ls, d);
                 int32_t v = 0;
-                if (val) v = d == 0 ? (int32_t)idx : ((const int32_t*)rlp(my_tadj, d))[idx];
-                const int32_t g = (val && rl(my_need, d)) ? gid[v] : -1;
+                if (val) v = d == 0 ? (int32_t)idx : (src < 0 ? tadj[idx] : D->nt[src].adj[idx]);
+                const int32_t g = (val && rl(my_need, d)) ? (src < 0 ? gid[v] : D->nt[src].adj_gid[idx]) : -1;
                 bool ok = val;
                 uint32_t same = rl(my_same, d);
                 while (same) {
@@ -493,15 +562,24 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 while (ntm) {
                     const int jj = __ffs(ntm) - 1;
                     ntm &= ntm - 1;
-                    const NtDesc& N = D->nt[e++];
+                    const int ei = (int)e++;
+                    if (ei == src) continue;  // the list these candidates came from
+                    const NtDesc& N = D->nt[ei];
                     const int32_t x = rl(pl, jj);
                     if (ok) ok = contains(N.adj_gid, N.off[x], N.off[x + 1], g);
+                }
+                if (src >= 0 && ok) {
+                    // read from a non-tree list: the tree edge is the check
+                    const int64_t* toff = (const int64_t*)rlp(my_toff, d);
+                    const int32_t xp = rl(pl, rl(my_par, d));
+                    ok = in_tree_list(tadj, gid, toff[xp], toff[xp + 1], g);
                 }
                 const uint64_t m = __ballot(ok);
                 {
                     const uint64_t nv = (uint64_t)__popcll(__ballot(val));
                     nN += nv;
                     nM += nv * n_nt_here;
+                    ++nC;
                 }
                 lc = setl(lc, cur + (int64_t)CSTM_WAVE, lane, d);
                 if (d == k - 1) {
@@ -521,20 +599,20 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 } else if (d == k - 2 && sum_last) {
                     // unconstrained last level: every survivor adds its list length
                     if (m) {
-                        const uint64_t n = (uint64_t)flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff);
+                        const uint64_t n = (uint64_t)flat_total(A, D, d, ok, v, pl, my_par, my_toff, my_nt, my_ntf);
                         cnt += n;
                         nN += n;
                         nS += n;
                         nF += (uint64_t)__popcll(m);
                     }
                 } else if (m && ((d == k - 2) || (d == k - 3 && sum_last)) &&
-                           flat_total(A, D, d, ok, v, pl, lane, my_par, my_toff) <= A.flat_max) {
+                           flat_total(A, D, d, ok, v, pl, my_par, my_toff, my_nt, my_ntf) <= A.flat_max) {
                     // the next level flattened over all survivors of this chunk: the last
                     // level, or the second-to-last with the unconstrained last level summed
                     const bool sum_next = d == k - 3;
                     const uint64_t passed = flat_expand(A, D, k, d, ok, v, g, pl, pg, lane, my_par, my_toff, my_tadj,
                                                         my_gid, my_need, my_same, my_nt, my_ntf, my_u, sum_next, cnt,
-                                                        nN, nM, nS);
+                                                        nN, nM, nS, nC);
                     nF += (uint64_t)__popcll(m) + (sum_next ? passed : 0);
                 } else if (m) {
                     M = m;
@@ -619,17 +697,21 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
             M &= M - 1;
             lm = setl(lm, M, lane, d);
             const int64_t chunk = rl(lc, d) - (int64_t)CSTM_WAVE;
-            const int32_t v =
-                d == 0 ? (int32_t)(chunk + b) : ((const int32_t*)rlp(my_tadj, d))[chunk + b];
-            const int32_t g = rl(my_need, d) ? ((const int32_t*)rlp(my_gid, d))[v] : 0;
+            const int srcd = d == 0 ? -1 : rl(ls, d);
+            const int64_t at = chunk + b;
+            const int32_t v = d == 0 ? (int32_t)at
+                                     : (srcd < 0 ? ((const int32_t*)rlp(my_tadj, d))[at] : D->nt[srcd].adj[at]);
+            const int32_t g = rl(my_need, d)
+                                  ? (srcd < 0 ? ((const int32_t*)rlp(my_gid, d))[v] : D->nt[srcd].adj_gid[at])
+                                  : 0;
             pl = setl(pl, v, lane, d);
             pg = setl(pg, g, lane, d);
             ++d;
-            const int p = rl(my_par, d);
-            const int64_t* toff = (const int64_t*)rlp(my_toff, d);
-            const int32_t x = rl(pl, p);
-            lc = setl(lc, toff[x], lane, d);
-            le = setl(le, toff[x + 1], lane, d);
+            int64_t nlo, nhi;
+            const int nsrc = pick_list(D, d, d - 1, v, pl, my_par, my_toff, my_nt, my_ntf, nlo, nhi);
+            lc = setl(lc, nlo, lane, d);
+            le = setl(le, nhi, lane, d);
+            ls = setl(ls, (int32_t)nsrc, lane, d);
             lm = setl(lm, (uint64_t)0, lane, d);
         }
         if (lane == 0) atomicAdd(&A.qu->outstanding.v, ~0ull);
@@ -645,6 +727,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
         atomicAdd(&A.stats[5], (unsigned long long)t_wait);
         atomicAdd(&A.stats[6], (unsigned long long)t_busy);
         atomicAdd(&A.stats[7], (unsigned long long)nS);
+        atomicAdd(&A.stats[8], (unsigned long long)nC);
     }
 }
 
@@ -687,6 +770,9 @@ void zero_words(void* p, size_t bytes, hipStream_t s) {
     k_zero_words<<<cstm_blocks((int64_t)n, 256, 2048), 256, 0, s>>>((uint32_t*)p, n);
     HIP_TRY(hipGetLastError());
 }
+
+// Work counters of a launch (GArgs::stats).
+constexpr int kWorkSlots = 9;
 
 // Task-ring size of launches in a caller's fixed workspace: 2^16 slots.
 constexpr int kFixedQlog = 16;
@@ -755,7 +841,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     const size_t off_ready = up(qcap * sizeof(GTask));
     const size_t off_qu = up(off_ready + qcap * sizeof(unsigned int));
     const size_t off_work = up(off_qu + sizeof(GQueue));
-    const size_t off_desc = up(off_work + 8 * sizeof(unsigned long long));
+    const size_t off_desc = up(off_work + kWorkSlots * sizeof(unsigned long long));
     const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
     const size_t off_slot = up(off_meta + (4 * (size_t)ns + 1) * sizeof(int64_t));
     const size_t off_segq = up(off_slot + (size_t)nq * sizeof(int32_t));
@@ -804,7 +890,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     for (int q = 0; q < nq; ++q)
         HIP_TRY(hipMemcpyAsync(descs + q, &csts[q]->host_desc, sizeof(CstDev), hipMemcpyHostToDevice, s));
     zero_words(ready, ready_b, s);
-    zero_words(work, 8 * sizeof(unsigned long long), s);
+    zero_words(work, kWorkSlots * sizeof(unsigned long long), s);
     GQueue init;
     std::memset(&init, 0, sizeof(init));
     init.tail.v = total;
@@ -866,7 +952,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
     }
-    unsigned long long h[8];
+    unsigned long long h[kWorkSlots];
     GQueue fin{};
     HIP_TRY(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&fin, qu, sizeof(fin), hipMemcpyDeviceToHost, s));
@@ -881,6 +967,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     st->pushed += h[4];
     st->busy_frac = (h[5] + h[6]) ? (double)h[6] / (double)(h[5] + h[6]) : 0.0;
     st->summed += h[7];
+    st->chunks += h[8];
     {
         std::lock_guard<std::mutex> lk(ctx->ws_mu);
         ctx->last_enum = *st;  // kept even when the launch is reported as failed below

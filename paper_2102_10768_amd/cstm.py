@@ -46,6 +46,7 @@ class cstm_tune(ctypes.Structure):
         ("hbm_donate_min", ctypes.c_int32),
         ("batch_order", ctypes.c_int32),
         ("hbm_idle_ms", ctypes.c_int32),
+        ("order_rule", ctypes.c_int32),
     ]
 
 
@@ -64,6 +65,7 @@ class cstm_enum_stats(ctypes.Structure):
         ("pushed", ctypes.c_uint64),
         ("busy_frac", ctypes.c_double),
         ("summed", ctypes.c_uint64),
+        ("chunks", ctypes.c_uint64),
     ]
 
 

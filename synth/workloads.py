@@ -28,10 +28,15 @@ POWER_LAW_1M = {
 
 RMAT_22 = {
     "name": "c3",
-    "title": "R-MAT scale 22 (a,b,c = .57,.19,.19), 64 uniform labels; 1000 screened queries of 4..16 vertices",
+    "title": "R-MAT scale 22 (a,b,c = .57,.19,.19), 64 uniform labels; 1000 random-walk queries of 4..16 vertices, "
+             "each counting min(#embeddings, 10^8)",
     "graph": {"kind": "rmat", "scale": 22, "edge_factor": 16, "a": 0.57, "b": 0.19, "c": 0.19, "seed": 13,
               "labels": {"kind": "uniform", "L": 64}},
-    "queries": {"k_min": 4, "k_max": 16, "count": 1000, "seed": 23},
+    # exactly the 1,000 drawn walks (sizes uniform in 4..16); most walks of six or
+    # more vertices have 10^9 to 10^17 embeddings here, so each asks for
+    # min(#embeddings, limit), which the oracle counts exactly
+    "queries": {"k_min": 4, "k_max": 16, "count": 1000, "seed": 23, "limit": 100_000_000, "fixed_draws": True,
+                "screen_budget": 15_000_000_000},
 }
 
 SERVE_16M = {
@@ -56,7 +61,8 @@ BILLION = {
     # every one of these random walks has far more embeddings than any search
     # can visit (the oracle's partial counts pass 10^8 within seconds), so each
     # query asks for min(#embeddings, limit); the stored counts come from the oracle
-    "queries": {"k_min": 12, "k_max": 32, "count": 200, "seed": 25, "limit": 1_000_000_000},
+    "queries": {"k_min": 12, "k_max": 32, "count": 200, "seed": 25, "limit": 1_000_000_000, "fixed_draws": True,
+                "screen_budget": 150_000_000_000},
 }
 
 ALL = {w["name"]: w for w in (SMALL, POWER_LAW_1M, RMAT_22, SERVE_16M, BILLION)}

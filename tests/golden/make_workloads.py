@@ -2,7 +2,7 @@
 
     python tests/golden/make_workloads.py c1
     python tests/golden/make_workloads.py c2 [--budget 200000000] [--count-cap 20000000000]
-    python tests/golden/make_workloads.py c5 [--budget 150000000000] [--threads 0]
+    python tests/golden/make_workloads.py c3|c5 [--budget N] [--threads 0] [--unlimited-s 2]
 
 Expected values come from the CPU oracle (``oracle``); inputs come only
 from ``synth``.  For the sparse class of c2 the expected count is the exact
@@ -66,10 +66,15 @@ def make_small(w: dict):
                       "queries": out})
 
 
-def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap: int, dense_tries: int):
-    """Screen random walks into the sparse and dense classes (see the module docstring)."""
+def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap: int, dense_tries: int,
+                  dense_seconds: float):
+    """Screen random walks into the sparse and dense classes (see the module docstring).
+    Dense tries stop after dense_tries attempts or once they have used
+    dense_seconds of oracle time (0: no time cap)."""
     g = make_graph(w["graph"])
     print("graph", g.summary(), flush=True)
+    lcol = oracle.label_grouped_col(g, threads=threads)
+    dense_spent = 0.0
     exact = cf.ExactTreeCounter(g)
     spec = w["queries"]
     quota = {"sparse": int(spec["sparse"]), "dense": int(spec["dense"])}
@@ -101,13 +106,14 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
                 continue
             d.update(draw=draw, kind=cls, count=c, expected_from="tree_dp")
         else:
-            if stats["dense_tried"] >= dense_tries:
+            if stats["dense_tried"] >= dense_tries or (dense_seconds and dense_spent >= dense_seconds):
                 stats["dense_not_tried"] += 1
                 continue
             stats["dense_tried"] += 1
             t = time.time()
-            r = oracle.match(g, q, node_budget=budget, threads=threads)
+            r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol)
             dt = time.time() - t
+            dense_spent += dt
             if r.status != oracle.OK:
                 stats["dense_over_budget"] += 1
                 print(f"draw {draw} dense m_q={q.m_q} over budget ({dt:.1f}s)", flush=True)
@@ -126,9 +132,11 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
         "graph_summary": g.summary(),
         "screen": {"sparse_rule": "tree query with pairwise-distinct labels and at most count_cap embeddings "
                                   "(exact count: labelled tree homomorphism DP)",
-                   "dense_rule": "oracle finishes within node_budget visited partial embeddings",
+                   "dense_rule": "oracle (label-grouped rows) finishes within node_budget work units",
                    "count_cap": count_cap, "node_budget": budget, "max_draws": max_draws,
-                   "dense_tries": dense_tries, **stats, "short": {c: quota[c] - len(got[c]) for c in quota}},
+                   "dense_tries": dense_tries, "dense_seconds_cap": dense_seconds,
+                   "dense_oracle_seconds": round(dense_spent, 1), **stats,
+                   "short": {c: quota[c] - len(got[c]) for c in quota}},
         "oracle": {"threads": threads or oracle.num_cores()},
         "queries": queries,
     })
@@ -186,7 +194,7 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
 
 
 def make_fixed_draws(w: dict, budget: int, threads: int, unlimited_s: float):
-    """Billion-edge workload: exactly the configured number of random walks
+    """Batch and billion-edge workloads: exactly the configured number of random walks
     (sizes uniform in [k_min, k_max]), every one kept, none redrawn.  Each
     asks for min(#embeddings, limit); the oracle (label-grouped rows) screens
     each within node_budget work units.  Queries it finishes get their stored
@@ -252,18 +260,21 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--count-cap", type=int, default=20_000_000_000)
     ap.add_argument("--dense-tries", type=int, default=100)
+    ap.add_argument("--dense-seconds", type=float, default=0.0,
+                    help="c2: stop trying dense draws after this much oracle time (0: no cap)")
     ap.add_argument("--unlimited-s", type=float, default=2.0,
                     help="c5: seconds of an unlimited oracle run per query before the limited screen (0: skip)")
     a = ap.parse_args()
     w = ALL[a.name]
-    if w["name"] == "c5":
-        make_fixed_draws(w, a.budget if a.budget != 200_000_000 else 150_000_000_000, a.threads, a.unlimited_s)
+    if w["queries"].get("fixed_draws"):
+        default_budget = int(w["queries"].get("screen_budget", 150_000_000_000))
+        make_fixed_draws(w, a.budget if a.budget != 200_000_000 else default_budget, a.threads, a.unlimited_s)
     elif "sizes" in w["queries"]:
         make_small(w)
     elif "k_min" in w["queries"]:
         make_batch(w, a.budget, a.max_draws, a.threads)
     else:
-        make_screened(w, a.budget, a.max_draws, a.threads, a.count_cap, a.dense_tries)
+        make_screened(w, a.budget, a.max_draws, a.threads, a.count_cap, a.dense_tries, a.dense_seconds)
 
 
 if __name__ == "__main__":
