@@ -356,6 +356,7 @@ int oracle_match(int64_t n, const int64_t* row_ptr, const int32_t* col, const in
         else {
             uint64_t off = 0;
             for (int t = 0; t < nt; ++t) {
+                if (!ws[t].nrows) continue;  /* a worker that found nothing holds no row buffer */
                 memcpy(all + off * (uint64_t)k, ws[t].rows, ws[t].nrows * (uint64_t)k * sizeof(int32_t));
                 off += ws[t].nrows;
             }

@@ -193,12 +193,15 @@ def make_batch(w: dict, budget: int, max_draws: int, threads: int):
     })
 
 
-def make_fixed_draws(w: dict, budget: int, threads: int, unlimited_s: float):
+def make_fixed_draws(w: dict, budget: int, threads: int, unlimited_s: float, deadline_s: float):
     """Batch and billion-edge workloads: exactly the configured number of random walks
     (sizes uniform in [k_min, k_max]), every one kept, none redrawn.  Each
     asks for min(#embeddings, limit); the oracle (label-grouped rows) screens
-    each within node_budget work units.  Queries it finishes get their stored
-    count; the others are recorded as INF (no count) and stay out of parity."""
+    each within node_budget work units and deadline_s seconds.  Queries it
+    finishes get their stored count; the others are recorded as INF (no
+    count) and stay out of parity.  Progress is appended to
+    <name>.partial.jsonl next to the output, and a rerun skips the queries
+    already there (the file is removed once the set is written)."""
     t_start = time.time()
     g = make_graph(w["graph"], log=lambda m: print(m, flush=True))
     print("graph", g.summary(), f"({time.time() - t_start:.0f}s)", flush=True)
@@ -210,46 +213,75 @@ def make_fixed_draws(w: dict, budget: int, threads: int, unlimited_s: float):
     for _ in range(int(spec["count"])):
         k = int(rng.integers(int(spec["k_min"]), int(spec["k_max"]) + 1))
         qs.append(random_walk_query(g, k, rng))
-    # first, without the limit: does any query finish within unlimited_s seconds?
-    unlimited = []
-    for i, q in enumerate(qs):
-        if unlimited_s <= 0:
-            break
-        r = oracle.match(g, q, deadline_s=unlimited_s, threads=threads, lcol=lcol)
-        unlimited.append({"finished": r.status == oracle.OK, "count_at_stop": r.count})
-        print(f"unlimited query {i}: {'finished' if r.status == oracle.OK else 'INF'} {r.count}", flush=True)
+    partial = os.path.join(HERE, f"{w['name']}.partial.jsonl")
+    done, unl = {}, {}
+    if os.path.exists(partial):
+        for line in open(partial):
+            d = json.loads(line)
+            (unl if d.get("unlimited") else done)[int(d["qid"])] = d
+        print(f"resuming: {len(unl)} unlimited and {len(done)} limited runs already made", flush=True)
     out, inf = [], []
     oracle_s = 0.0
-    for i, q in enumerate(qs):
-        t = time.time()
-        r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol, limit=limit)
-        dt = time.time() - t
-        oracle_s += dt
-        d = q.to_dict()
-        d.update(draw=i, qid=i, nodes=r.nodes, oracle_s=round(dt, 3), limit=limit)
-        if r.status == oracle.OK:
-            d.update(count=r.count, expected_from="oracle")
-        else:
-            d.update(count=None, partial=r.count, expected_from="INF")
-            inf.append(i)
-        out.append(d)
-        print(f"query {i} k={q.k} m_q={q.m_q}: {'INF' if d['count'] is None else d['count']} "
-              f"in {dt:.1f}s ({len(inf)} INF so far)", flush=True)
+    with open(partial, "a") as pf:
+        # first, without the limit: does any query finish within unlimited_s seconds?
+        unlimited = []
+        for i, q in enumerate(qs):
+            if unlimited_s <= 0:
+                break
+            if i not in unl:
+                r = oracle.match(g, q, deadline_s=unlimited_s, threads=threads, lcol=lcol)
+                unl[i] = {"qid": i, "unlimited": True, "finished": r.status == oracle.OK, "count_at_stop": r.count}
+                pf.write(json.dumps(unl[i]) + "\n")
+                pf.flush()
+            unlimited.append(unl[i])
+            print(f"unlimited query {i}: {'finished' if unl[i]['finished'] else 'INF'} {unl[i]['count_at_stop']}",
+                  flush=True)
+        for i, q in enumerate(qs):
+            if i in done:
+                d = q.to_dict()
+                d.update(done[i])
+            else:
+                t = time.time()
+                r = oracle.match(g, q, node_budget=budget, deadline_s=deadline_s, threads=threads, lcol=lcol,
+                                 limit=limit)
+                dt = time.time() - t
+                d = q.to_dict()
+                d.update(draw=i, qid=i, nodes=r.nodes, oracle_s=round(dt, 3), limit=limit)
+                if r.status == oracle.OK:
+                    d.update(count=r.count, expected_from="oracle")
+                else:
+                    d.update(count=None, partial=r.count, expected_from="INF")
+                pf.write(json.dumps(d) + "\n")
+                pf.flush()
+            oracle_s += float(d["oracle_s"])
+            if d["count"] is None:
+                inf.append(i)
+            out.append(d)
+            print(f"query {i} k={q.k} m_q={q.m_q}: {'INF' if d['count'] is None else d['count']} "
+                  f"in {d['oracle_s']:.1f}s ({len(inf)} INF so far)", flush=True)
+    screen = {"rule": f"every drawn query kept; the oracle (label-grouped rows) must reach min(total, {limit}) "
+                      "within node_budget work units and deadline_s seconds, else the query is INF and has no "
+                      "stored count",
+              "node_budget": budget, "deadline_s": deadline_s, "inf": inf, "oracle_seconds": round(oracle_s, 1),
+              "sizes": {str(k): sum(1 for d in out if len(d["qlabel"]) == k)
+                        for k in range(int(spec["k_min"]), int(spec["k_max"]) + 1)},
+              "sizes_with_count": {str(k): sum(1 for d in out if len(d["qlabel"]) == k and d["count"] is not None)
+                                   for k in range(int(spec["k_min"]), int(spec["k_max"]) + 1)},
+              "seconds": round(time.time() - t_start, 1)}
+    if unlimited:
+        screen["unlimited_screen"] = {
+            "seconds_per_query": unlimited_s, "finished": sum(u["finished"] for u in unlimited),
+            "tried": len(unlimited),
+            "min_count_at_stop": min(u["count_at_stop"] for u in unlimited),
+            "max_count_at_stop": max(u["count_at_stop"] for u in unlimited)}
     write(w["name"], {
         "workload": w,
         "graph_summary": g.summary(),
-        "screen": {"rule": f"every drawn query kept; the oracle (label-grouped rows) must reach min(total, {limit}) "
-                           "within node_budget work units, else the query is INF and has no stored count",
-                   "node_budget": budget, "inf": inf, "oracle_seconds": round(oracle_s, 1),
-                   "unlimited_screen": {"seconds_per_query": unlimited_s,
-                                        "finished": sum(u["finished"] for u in unlimited),
-                                        "tried": len(unlimited),
-                                        "min_count_at_stop": min((u["count_at_stop"] for u in unlimited), default=None),
-                                        "max_count_at_stop": max((u["count_at_stop"] for u in unlimited), default=None)},
-                   "seconds": round(time.time() - t_start, 1)},
+        "screen": screen,
         "oracle": {"threads": threads or oracle.num_cores()},
         "queries": out,
     })
+    os.remove(partial)
 
 
 def main():
@@ -262,13 +294,16 @@ def main():
     ap.add_argument("--dense-tries", type=int, default=100)
     ap.add_argument("--dense-seconds", type=float, default=0.0,
                     help="c2: stop trying dense draws after this much oracle time (0: no cap)")
+    ap.add_argument("--deadline-s", type=float, default=300.0,
+                    help="c3/c5: oracle seconds per query before it counts as INF")
     ap.add_argument("--unlimited-s", type=float, default=2.0,
                     help="c5: seconds of an unlimited oracle run per query before the limited screen (0: skip)")
     a = ap.parse_args()
     w = ALL[a.name]
     if w["queries"].get("fixed_draws"):
         default_budget = int(w["queries"].get("screen_budget", 150_000_000_000))
-        make_fixed_draws(w, a.budget if a.budget != 200_000_000 else default_budget, a.threads, a.unlimited_s)
+        make_fixed_draws(w, a.budget if a.budget != 200_000_000 else default_budget, a.threads, a.unlimited_s,
+                         a.deadline_s)
     elif "sizes" in w["queries"]:
         make_small(w)
     elif "k_min" in w["queries"]:

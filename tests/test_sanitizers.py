@@ -1,0 +1,27 @@
+"""The host C code (CPU oracle, native input generator) under AddressSanitizer
+and UndefinedBehaviorSanitizer: built with gcc on the host (no GPU code is
+involved) and run on inputs with closed-form answers (``sanitize_driver.c``)."""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_oracle_and_generator_under_asan_and_ubsan(tmp_path):
+    exe = tmp_path / "sanitized"
+    srcs = [os.path.join(ROOT, "tests", "sanitize_driver.c"), os.path.join(ROOT, "oracle", "oracle.c"),
+            os.path.join(ROOT, "synth", "rmat_native.c")]
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=gnu11", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                           "-fno-sanitize-recover=all", "-pthread", *srcs, "-o", str(exe)])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ok" in r.stdout
