@@ -364,9 +364,13 @@ cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, i
  * mem_budget; builds admitted CSTs on `builders` threads, each with its own
  * stream; and gives every built CST to the next free enumeration lane, which
  * counts all CSTs built so far (up to max_batch) in one persistent launch on
- * its own stream.  Several lanes run launches at the same time.  A request's
- * count does not depend on which requests share its launch.  The server is
- * thread-safe; it uses the context's tuning (deadline_ms applies per launch).
+ * its own stream, reading the CSTs from device memory whatever the context's
+ * enum_mode (so no partition images exceed what admission charged).  Each
+ * lane's launch workspace (its task ring) is charged to mem_budget once, when
+ * the server is created.  Several lanes run launches at the same time.  A
+ * request's count does not depend on which requests share its launch.  The
+ * server is thread-safe; it uses the context's tuning (deadline_ms applies
+ * per launch).
  * Zero or negative lanes / builders / max_batch take the defaults 2 / 2 / 256
  * (lanes + builders streams: HIP maps a process's streams onto a few
  * hardware queues, 4 by default, and streams sharing one queue run in
@@ -375,7 +379,8 @@ cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, i
  * running a launch (the server is under load) and more requests are on their
  * way, it waits up to this long for more to join its launch; an idle server
  * launches at once (0: never wait).
- * Errors: CSTM_EINVAL for NULL arguments or a graph of another context. */
+ * Errors: CSTM_EINVAL for NULL arguments or a graph of another context;
+ * CSTM_ENOMEM when mem_budget does not cover the lanes' task rings. */
 typedef struct cstm_server cstm_server;
 typedef struct {
     int32_t done;        /* 1: finished; the fields below are set                   */

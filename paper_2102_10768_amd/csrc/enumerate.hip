@@ -413,7 +413,7 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
         cstm_cst* c = csts[q];
         if (c->empty) continue;
         int mode = T.enum_mode;
-        if (o.root_ranges) mode = CSTM_MODE_HBM;
+        if (o.root_ranges || o.force_hbm) mode = CSTM_MODE_HBM;
         if (mode == CSTM_MODE_AUTO) {
             // partitions the caller asked for are enumerated on chip; otherwise the
             // CST stays in HBM, where the whole GPU shares one query's search

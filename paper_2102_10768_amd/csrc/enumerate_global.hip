@@ -774,10 +774,39 @@ void zero_words(void* p, size_t bytes, hipStream_t s) {
 // Work counters of a launch (GArgs::stats).
 constexpr int kWorkSlots = 9;
 
+// Layout of a launch's workspace, every region 256-byte aligned and sized by
+// sizeof(): ring | ready flags | queue state | work counters | descriptors |
+// seed tables | count slots | limits | stop flags.
+struct WsLayout {
+    size_t off_ready, off_qu, off_work, off_desc, off_meta, off_slot, off_segq, off_lim, off_stop, need;
+};
+WsLayout ws_layout(unsigned long long qcap, int nq, int ns) {
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    WsLayout L;
+    L.off_ready = up(qcap * sizeof(GTask));
+    L.off_qu = up(L.off_ready + qcap * sizeof(unsigned int));
+    L.off_work = up(L.off_qu + sizeof(GQueue));
+    L.off_desc = up(L.off_work + kWorkSlots * sizeof(unsigned long long));
+    L.off_meta = up(L.off_desc + (size_t)nq * sizeof(CstDev));
+    L.off_slot = up(L.off_meta + (4 * (size_t)ns + 1) * sizeof(int64_t));
+    L.off_segq = up(L.off_slot + (size_t)nq * sizeof(int32_t));
+    L.off_lim = up(L.off_segq + (size_t)ns * sizeof(int32_t));
+    L.off_stop = up(L.off_lim + (size_t)nq * sizeof(unsigned long long));
+    L.need = up(L.off_stop + (size_t)nq * sizeof(unsigned int));
+    return L;
+}
+
 // Task-ring size of launches in a caller's fixed workspace: 2^16 slots.
 constexpr int kFixedQlog = 16;
 
 }  // namespace
+
+// Device bytes the context lends one HBM-mode launch of nq CSTs (its
+// workspace, with the quarter of slack ws_acquire adds).
+size_t cstm_hbm_workspace_bytes(int nq) {
+    const size_t need = ws_layout(1ull << 20, nq, nq).need;
+    return need + need / 4;
+}
 
 // Count (or list) the embeddings of nq CSTs in one launch, the CSTs read from
 // HBM; counts go to counts_dev[slot[q]].
@@ -837,17 +866,10 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     if (total == 0) return;
     // workspace lent by the context for this launch, every region 256-byte aligned and sized by sizeof():
     // ring | ready flags | queue state | work counters | descriptors | seed tables | count slots
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t off_ready = up(qcap * sizeof(GTask));
-    const size_t off_qu = up(off_ready + qcap * sizeof(unsigned int));
-    const size_t off_work = up(off_qu + sizeof(GQueue));
-    const size_t off_desc = up(off_work + kWorkSlots * sizeof(unsigned long long));
-    const size_t off_meta = up(off_desc + (size_t)nq * sizeof(CstDev));
-    const size_t off_slot = up(off_meta + (4 * (size_t)ns + 1) * sizeof(int64_t));
-    const size_t off_segq = up(off_slot + (size_t)nq * sizeof(int32_t));
-    const size_t off_lim = up(off_segq + (size_t)ns * sizeof(int32_t));
-    const size_t off_stop = up(off_lim + (size_t)nq * sizeof(unsigned long long));
-    const size_t need = up(off_stop + (size_t)nq * sizeof(unsigned int));
+    const WsLayout Lw = ws_layout(qcap, nq, ns);
+    const size_t off_ready = Lw.off_ready, off_qu = Lw.off_qu, off_work = Lw.off_work, off_desc = Lw.off_desc;
+    const size_t off_meta = Lw.off_meta, off_slot = Lw.off_slot, off_segq = Lw.off_segq, off_lim = Lw.off_lim;
+    const size_t off_stop = Lw.off_stop, need = Lw.need;
     const size_t ready_b = qcap * sizeof(unsigned int);
     struct WsHold {
         cstm_ctx* ctx;

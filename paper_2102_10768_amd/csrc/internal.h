@@ -318,7 +318,11 @@ struct EnumOpts {
     // lent by the context
     void* fixed_ws = nullptr;
     size_t fixed_ws_bytes = 0;
+    // every CST of the call in device memory (no partitioning at launch), whatever tune.enum_mode says
+    bool force_hbm = false;
 };
+// Device bytes the context lends one HBM-mode launch of nq CSTs.
+size_t cstm_hbm_workspace_bytes(int nq);
 // Look up this device's copy of the no-allocation scratch array (once per
 // device, with the device current); cstm_ctx_create calls it.
 void cstm_noalloc_init(int device);

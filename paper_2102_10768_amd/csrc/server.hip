@@ -191,6 +191,7 @@ struct cstm_server {
                 EnumOpts o;
                 o.limits = any_limit ? limits.data() : nullptr;
                 o.deadline_ms = ctx->tune.deadline_ms;
+                o.force_hbm = true;  // admission charged the CSTs, not partition images
                 cstm_enumerate_run(ctx, (int)csts.size(), csts.data(), 0, nullptr, 0, counts.data(), nullptr, o, s);
             });
             {
@@ -215,11 +216,15 @@ extern "C" cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, ui
         if (max_batch <= 0) max_batch = 256;
         CSTM_REQUIRE(lanes <= 16 && builders <= 64, CSTM_EINVAL, "at most 16 lanes and 64 builders");
         CSTM_REQUIRE(mem_budget > 0, CSTM_EINVAL, "memory budget must be positive");
+        // every lane's launch borrows a task-ring workspace: charged once, up front
+        const uint64_t rings = (uint64_t)lanes * (uint64_t)cstm_hbm_workspace_bytes(max_batch);
+        CSTM_REQUIRE(mem_budget > rings, CSTM_ENOMEM,
+                     "memory budget does not cover the lanes' task rings (" + std::to_string(rings) + " bytes)");
         HIP_TRY(hipSetDevice(ctx->device));
         srv = new cstm_server();
         srv->ctx = ctx;
         srv->g = g;
-        srv->budget = mem_budget;
+        srv->budget = mem_budget - rings;
         srv->max_batch = max_batch;
         srv->batch_wait_us = batch_wait_us < 0 ? 0 : batch_wait_us;
         srv->t0 = Clock::now();

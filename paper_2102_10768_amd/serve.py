@@ -1,39 +1,18 @@
-"""Request loop for matching queries against one resident data graph.
+"""Driving the library's request server and its one-at-a-time baseline.
 
-The library implements this loop natively (``cstm_server_*``, bound as
-``cstm.Server``); ``replay_native`` drives it with a request stream.  The
-``Server`` class below is the same policy over a pluggable backend, used to
-test the policy on the host and to run it over custom backends.
-
-Requests (query graphs) arrive one at a time.  The loop
-
-* admits them in arrival order while their CSTs fit a device-memory budget
-  (each request is charged an upper bound on its CST build from the label
-  index, ``Graph.estimate_bytes``, doubled for the block cache's power-of-two
-  rounding; a request larger than the whole budget is refused),
-* builds each admitted request's CST as soon as it is admitted, on one of
-  several builder threads with a stream each, while earlier requests are
-  being enumerated,
-* hands every built CST to the next free enumeration lane: a lane takes all
-  CSTs built so far (up to ``max_batch``) and counts them in one persistent
-  launch on its own stream (``batch_count``); with two or more lanes a new
-  batch starts while a long one is still running, so requests that arrive
-  while others are on the GPU overlap with them instead of queueing behind
-  them,
-* returns each request's count as soon as its batch ends, frees its CST and
-  gives its memory back to admission.
-
-Counts do not depend on which requests share a batch: each CST is counted on
-its own, the batch only shares the launch.  ``run_sequential`` is the plain
-form for comparison: one request at a time, build then count, in arrival order.
-
-The device work goes through a backend object (``CstmBackend`` for the HIP
-library); tests substitute a host-only backend to check the loop's logic.
+The serving loop itself is native (``cstm_server_*``, bound as
+``cstm.Server``): it admits requests in arrival order while their CSTs fit a
+device-memory budget, builds admitted CSTs on builder threads (a stream
+each), and hands built CSTs to enumeration lanes that count everything built
+so far in one persistent launch each, several lanes at once.  This module
+replays a request stream against it (``replay_native``), runs the plain form
+for comparison (``run_sequential``: one request at a time, build then count,
+in arrival order, through a backend object), and summarizes latencies
+(arrival to result, nearest-rank p50/p99) and throughput.
 """
 
 from __future__ import annotations
 
-import collections
 import math
 import threading
 import time
@@ -71,7 +50,7 @@ class Request:
 
 
 class CstmBackend:
-    """Device work of the loop through the HIP library."""
+    """Device work of the one-at-a-time form through the HIP library."""
 
     def __init__(self, ctx, graph):
         import torch
@@ -97,170 +76,6 @@ class CstmBackend:
 
     def release(self, handle):
         handle.close()
-
-
-class Server:
-    """Continuous-batching loop (see the module docstring)."""
-
-    def __init__(self, backend, *, mem_budget: int = 64 << 30, lanes: int = 2, builders: int = 4,
-                 max_batch: int = 256, clock=time.perf_counter):
-        if lanes < 1 or builders < 1:
-            raise ValueError("lanes and builders must be at least 1")
-        self.backend = backend
-        self.mem_budget = int(mem_budget)
-        self.max_batch = int(max_batch)
-        self.clock = clock
-        self._cv = threading.Condition()
-        self._pending = collections.deque()  # arrived, not admitted
-        self._ready = collections.deque()  # built, not launched
-        self._in_use = 0  # bytes charged to admitted requests
-        self._peak = 0
-        self._busy_lanes = 0
-        self._max_overlap = 0
-        self._closing = False
-        self._next_id = 0
-        self.requests = []
-        self.batches = []  # (lane, size, seconds)
-        self._build_streams = [backend.new_stream() for _ in range(builders)]
-        self._lane_streams = [backend.new_stream() for _ in range(lanes)]
-        self._threads = [threading.Thread(target=self._build_loop, args=(st,), name=f"cstm-build{i}", daemon=True)
-                         for i, st in enumerate(self._build_streams)]
-        for i in range(lanes):
-            self._threads.append(threading.Thread(target=self._lane_loop, args=(i,), name=f"cstm-lane{i}",
-                                                  daemon=True))
-        for t in self._threads:
-            t.start()
-
-    # ------------------------------------------------------------ client side
-
-    def submit(self, query, t_arrival: float | None = None) -> Request:
-        with self._cv:
-            if self._closing:
-                raise RuntimeError("server is closed")
-            r = Request(self._next_id, query, self.clock() if t_arrival is None else t_arrival)
-            self._next_id += 1
-            self.requests.append(r)
-            self._pending.append(r)
-            self._cv.notify_all()
-        return r
-
-    def close(self, timeout: float | None = None):
-        """Finish every submitted request, then stop the threads."""
-        with self._cv:
-            self._closing = True
-            self._cv.notify_all()
-        for t in self._threads:
-            t.join(timeout)
-
-    def __enter__(self):
-        return self
-
-    def __exit__(self, *exc):
-        self.close()
-
-    @property
-    def peak_bytes(self) -> int:
-        """Largest total charge of admitted requests seen at one time."""
-        return self._peak
-
-    @property
-    def max_overlap(self) -> int:
-        """Most enumeration lanes that were running launches at one time."""
-        return self._max_overlap
-
-    # ------------------------------------------------------------ workers
-
-    def _finish(self, r: Request, count=None, error=None):
-        r.count = count
-        r.error = error
-        r.t_done = self.clock()
-        if r.handle is not None:
-            try:
-                self.backend.release(r.handle)
-            finally:
-                r.handle = None
-        with self._cv:
-            self._in_use -= r.charge
-            r.charge = 0
-            self._cv.notify_all()
-        r._event.set()
-
-    def _build_loop(self, stream):
-        while True:
-            refuse = None
-            with self._cv:
-                while True:
-                    while not self._pending and not self._closing:
-                        self._cv.wait()
-                    if not self._pending:
-                        self._cv.notify_all()  # let the lanes see that no more work comes
-                        return
-                    r = self._pending[0]
-                    if r.charge == 0:
-                        try:
-                            r.charge = max(1, int(self.backend.estimate(r.query)))
-                        except Exception as e:  # malformed query
-                            refuse = f"rejected: {e}"
-                    if refuse is None and r.charge > self.mem_budget:
-                        refuse = f"rejected: CST bound {r.charge} B exceeds the {self.mem_budget} B budget"
-                    if refuse is not None:
-                        self._pending.popleft()
-                        r.charge = 0
-                        break
-                    # admission in arrival order: the head request waits until it fits
-                    if self._in_use + r.charge <= self.mem_budget:
-                        self._pending.popleft()
-                        self._in_use += r.charge
-                        self._peak = max(self._peak, self._in_use)
-                        r.t_admit = self.clock()
-                        break
-                    self._cv.wait()
-            if refuse is not None:
-                self._finish(r, error=refuse)
-                continue
-            try:
-                r.handle = self.backend.build(r.query, stream)
-            except Exception as e:
-                self._finish(r, error=f"build failed: {e}")
-                continue
-            r.t_built = self.clock()
-            with self._cv:
-                self._ready.append(r)
-                self._cv.notify_all()
-
-    def _lane_loop(self, lane: int):
-        stream = self._lane_streams[lane]
-        while True:
-            with self._cv:
-                while not self._ready and not (self._closing and self._drained()):
-                    self._cv.wait()
-                if not self._ready:
-                    self._cv.notify_all()
-                    return
-                batch = []
-                while self._ready and len(batch) < self.max_batch:
-                    batch.append(self._ready.popleft())
-                self._busy_lanes += 1
-                self._max_overlap = max(self._max_overlap, self._busy_lanes)
-            t0 = self.clock()
-            for r in batch:
-                r.t_launch = t0
-                r.batch_size = len(batch)
-                r.lane = lane
-            try:
-                counts = self.backend.count_batch([r.handle for r in batch], stream)
-                err = None
-            except Exception as e:
-                counts, err = [None] * len(batch), f"enumeration failed: {e}"
-            with self._cv:
-                self._busy_lanes -= 1
-            self.batches.append((lane, len(batch), self.clock() - t0))
-            for r, c in zip(batch, counts):
-                self._finish(r, count=None if err else int(c), error=err)
-
-    def _drained(self) -> bool:
-        # called with the lock held: nothing waits for admission and the builder is idle
-        return not self._pending and all(r.t_built is not None or r.done for r in self.requests)
 
 
 def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):
@@ -290,20 +105,6 @@ def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.per
         r._event.set()
         out.append(r)
     return out
-
-
-def replay(server: Server, arrivals, queries, *, clock=time.perf_counter):
-    """Submit ``queries[i]`` at ``arrivals[i]`` seconds after the start; wait for all."""
-    start = clock()
-    reqs = []
-    for t, q in zip(arrivals, queries):
-        now = clock() - start
-        if now < t:
-            time.sleep(t - now)
-        reqs.append(server.submit(q, t_arrival=start + t))
-    for r in reqs:
-        r.wait()
-    return reqs
 
 
 def replay_native(server, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):

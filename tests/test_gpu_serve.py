@@ -31,38 +31,6 @@ def _load(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("name,n_req,qps", [("c1", 120, 3000.0), ("c2", 24, 40.0)])
-def test_served_results_equal_results_alone(name, n_req, qps):
-    from paper_2102_10768_amd import cstm, serve
-
-    W = _load(name)
-    g = make_graph(W["workload"]["graph"])
-    G = gpu_graph(g, "hbm")
-    c = ctx("hbm")
-    pool = [Query.from_dict(d) for d in W["queries"]]
-    expected = [int(d["count"]) for d in W["queries"]]
-    rng = np.random.Generator(np.random.PCG64(202))
-    picks = rng.integers(0, len(pool), size=n_req)
-    if name == "c2":
-        picks = rng.choice(np.argsort(expected)[: len(pool) // 2], size=n_req)  # the lighter half
-    alone = {}
-    for i in sorted(set(int(p) for p in picks)):
-        cs = cstm.CST(c, G, pool[i].qlabel, pool[i].qedges)
-        alone[i] = cs.count()
-        cs.close()
-        assert alone[i] == expected[i]
-    arr = serve.poisson_arrivals(n_req, qps, 203)
-    say(f"{name}: {n_req} requests at {qps} QPS over {len(alone)} distinct queries")
-    with serve.Server(serve.CstmBackend(c, G), mem_budget=8 << 30, lanes=2, max_batch=64) as srv:
-        reqs = serve.replay(srv, arr, [pool[int(p)] for p in picks])
-    s = serve.summarize(reqs)
-    say(f"{name}: {s} overlap {srv.max_overlap}")
-    for r, p in zip(reqs, picks):
-        assert r.error is None, r.error
-        assert r.count == alone[int(p)]
-    assert srv.peak_bytes <= 8 << 30
-
-
 @pytest.mark.parametrize("name,n_req,qps,wait_us", [("c1", 200, 4000.0, 0), ("c1", 200, 4000.0, 2000),
                                                      ("c2", 24, 40.0, 2000)])
 def test_native_server_results_equal_results_alone(name, n_req, qps, wait_us):
