@@ -413,6 +413,44 @@ def cpu_model() -> str:
     return ""
 
 
+def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> dict:
+    """Measured HBM stream-copy rate: a device-to-device copy of nbytes (read
+    plus write), timed with HIP events over reps copies.  Also the plain copy
+    of known size that the HBM counters are calibrated against."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_copied": nbytes, "ms_per_copy": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9,
+            "frac_of_peak": 2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def profile_launch(a):
+    """One batched step of the workload (every CST built, one launch) with the
+    given tuning and nothing else, for rocprofv3 runs; prints one JSON line."""
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries)
+    if a.tune:
+        S.ctx.tune = json.loads(a.tune)
+    counts, st, tb, _ = S.batched_step()
+    bad = S.bad(counts)
+    print(json.dumps({"workload": a.workload, "queries": len(S.queries), "embeddings": sum(counts),
+                      "mismatches": len(bad), "build_s": tb, "kernel_ms": st["kernel_ms"],
+                      "tune": S.ctx.tune}), flush=True)
+    S.close()
+    if bad:
+        sys.exit(1)
+
+
 def extra_workload(a, name):
     """Plain and batched forms of another stored workload (and, for the
     power-law one, a short served-vs-plain comparison)."""
@@ -485,12 +523,21 @@ def main():
     ap.add_argument("--share", default="", help="comma-separated deltas: sweep the host-core share (Algorithm 3)")
     ap.add_argument("--host-threads", type=int, default=0, help="--share: host threads (0: the host's cores, <= 16)")
     ap.add_argument("--orders", type=int, default=0, help="matching-order study: random tree orders per query")
+    ap.add_argument("--copy-probe", action="store_true", help="only the HBM stream-copy probe (one JSON line)")
+    ap.add_argument("--profile-launch", action="store_true",
+                    help="only one batched step of --workload (for rocprofv3 runs; one JSON line)")
+    ap.add_argument("--tune", default="", help="tuning (JSON dict of cstm_tune fields) for --profile-launch")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "
               f"in the design notes and is not built.", file=sys.stderr)
         sys.exit(2)
 
+    if a.copy_probe:
+        print(json.dumps(copy_ceiling()), flush=True)
+        return
+    if a.profile_launch:
+        return profile_launch(a)
     if a.serve or a.share or a.orders:
         from synth import make_graph
 
@@ -506,6 +553,7 @@ def main():
         return orders_main(a, W, g, queries, expected)
 
     out, bad = headline(a)
+    out["hbm_copy_ceiling"] = copy_ceiling()
     extras = {}
     for name in [x for x in a.extras.split(",") if x and x != a.workload]:
         row, bad_x = extra_workload(a, name)

@@ -405,6 +405,8 @@ typedef struct {
     uint64_t in_use_bytes;
     int32_t max_overlap; /* most lanes running launches at one time                 */
     int32_t reserved;
+    uint64_t admission_bytes; /* what admission may charge: mem_budget less the lanes'
+                                 task rings                                          */
 } cstm_server_stats;
 
 cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, uint64_t mem_budget, int32_t lanes,

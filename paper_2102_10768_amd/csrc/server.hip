@@ -303,6 +303,7 @@ extern "C" cstm_status cstm_server_get_stats(cstm_server* srv, cstm_server_stats
         std::lock_guard<std::mutex> lk(srv->mu);
         *out = srv->st;
         out->in_use_bytes = srv->in_use;
+        out->admission_bytes = srv->budget;
     });
 }
 

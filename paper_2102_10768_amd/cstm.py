@@ -113,6 +113,7 @@ class cstm_server_stats(ctypes.Structure):
         ("in_use_bytes", ctypes.c_uint64),
         ("max_overlap", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("admission_bytes", ctypes.c_uint64),
     ]
 
 

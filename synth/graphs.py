@@ -269,7 +269,7 @@ def zipf_labels(n: int, num_labels: int, s: float, seed: int) -> np.ndarray:
 def make_graph(spec: dict, log=None) -> Graph:
     """Build a graph from a plain dict spec.
 
-    ``{"kind": "er", "n", "p"}``, ``{"kind": "chung_lu", "n", "m", "gamma"}`` or
+    ``{"kind": "er", "n", "p"}``, ``{"kind": "chung_lu" | "chung_lu_native", "n", "m", "gamma"}`` or
     ``{"kind": "rmat" | "rmat_native", "scale", "edge_factor", "a", "b", "c"}``, each with
     ``"seed"`` and ``"labels": {"kind": "uniform"|"zipf", "L", ["s"]}``.
     """
@@ -281,6 +281,15 @@ def make_graph(spec: dict, log=None) -> Graph:
     elif kind == "chung_lu":
         n = int(spec["n"])
         row_ptr, col = chung_lu(n, int(spec["m"]), float(spec["gamma"]), seed, log=log)
+    elif kind == "chung_lu_native":
+        from . import native
+
+        n = int(spec["n"])
+        if log:
+            log(f"chung_lu (native): n {n}, m {spec['m']}")
+        row_ptr, col = native.chung_lu_csr(n, int(spec["m"]), float(spec["gamma"]), seed)
+        if log:
+            log(f"chung_lu (native): {col.shape[0] // 2} edges")
     elif kind == "rmat_native":
         from . import native
 

@@ -41,9 +41,10 @@ RMAT_22 = {
 
 SERVE_16M = {
     "name": "c4",
-    "title": "Chung-Lu 16M vertices, 256M edges, gamma 2.1, 100 Zipf(0.8) labels; "
+    "title": "Chung-Lu 16M vertices, 256M edges, gamma 2.1 (native generator), 100 Zipf(0.8) labels; "
              "screened pool of random-walk queries of 4..24 vertices, results limited to 10^6, Poisson arrivals",
-    "graph": {"kind": "chung_lu", "n": 16_000_000, "m": 256_000_000, "gamma": 2.1, "seed": 14,
+    # generated natively (counter-based SplitMix64, alias sampling, all host threads)
+    "graph": {"kind": "chung_lu_native", "n": 16_000_000, "m": 256_000_000, "gamma": 2.1, "seed": 14,
               "labels": {"kind": "zipf", "L": 100, "s": 0.8}},
     # each request asks for min(#embeddings, limit): on this graph almost every
     # random-walk query has far more embeddings than any search can visit

@@ -19,6 +19,8 @@ int oracle_label_group(int64_t n, const int64_t* row_ptr, const int32_t* col, co
                        int nthreads);
 int rmat_csr(int scale, int edge_factor, double a, double b, double c, uint64_t seed, int nthreads,
              int64_t** row_ptr_out, int32_t** col_out, int64_t* nnz_out);
+int chung_lu_csr(int64_t n, int64_t m, double gamma, uint64_t seed, int nthreads, int64_t** row_ptr_out,
+                 int32_t** col_out, int64_t* nnz_out);
 void rmat_free(void* p);
 
 static int fail(const char* what) {
@@ -61,23 +63,27 @@ int main(void) {
                          &written, &used) != 0 || cnt != 7)
             return fail("limit");
     }
-    /* R-MAT: simple, symmetric, sorted rows */
+    /* R-MAT and Chung-Lu: simple, symmetric, sorted rows; Chung-Lu with exactly m edges */
+    for (int which = 0; which < 2; ++which) {
     int64_t* rrp = NULL;
     int32_t* rcol = NULL;
     int64_t nnz = 0;
-    if (rmat_csr(10, 8, 0.57, 0.19, 0.19, 7, 3, &rrp, &rcol, &nnz)) return fail("rmat generation");
-    const int64_t n = 1 << 10;
-    if (rrp[n] != nnz) return fail("rmat row_ptr");
+    const int64_t n = which ? 1000 : 1 << 10;
+    if (which == 0 && rmat_csr(10, 8, 0.57, 0.19, 0.19, 7, 3, &rrp, &rcol, &nnz)) return fail("rmat generation");
+    if (which == 1 && (chung_lu_csr(n, 3000, 2.2, 9, 3, &rrp, &rcol, &nnz) || nnz != 6000))
+        return fail("chung-lu generation");
+    if (rrp[n] != nnz) return fail("row_ptr");
     for (int64_t v = 0; v < n; ++v)
         for (int64_t j = rrp[v]; j < rrp[v + 1]; ++j) {
             const int32_t w = rcol[j];
-            if (w == v || (j > rrp[v] && rcol[j - 1] >= w)) return fail("rmat row order");
+            if (w == v || (j > rrp[v] && rcol[j - 1] >= w)) return fail("row order");
             int found = 0;
             for (int64_t i = rrp[w]; i < rrp[w + 1]; ++i) found |= rcol[i] == (int32_t)v;
-            if (!found) return fail("rmat symmetry");
+            if (!found) return fail("symmetry");
         }
     rmat_free(rrp);
     rmat_free(rcol);
+    }
     printf("sanitized oracle and generator: ok\n");
     return 0;
 }

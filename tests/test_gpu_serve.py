@@ -73,7 +73,15 @@ def test_native_server_refuses_a_request_larger_than_the_budget():
     G = gpu_graph(g, "hbm")
     q = Query.from_dict(W["queries"][0])
     est = G.estimate_bytes(q.qlabel, q.qedges)
-    with cstm.Server(ctx("hbm"), G, mem_budget=est, lanes=1, builders=1) as srv:
+    # the lanes' task rings are charged when the server is created
+    with cstm.Server(ctx("hbm"), G, mem_budget=8 << 30, lanes=1, builders=1) as srv:
+        rings = (8 << 30) - srv.stats()["admission_bytes"]
+    assert rings > 0
+    with pytest.raises(cstm.CstmError) as ei:
+        cstm.Server(ctx("hbm"), G, mem_budget=rings, lanes=1, builders=1)
+    assert ei.value.status == cstm.ENOMEM
+    # a request whose charge (twice its bound, plus one) exceeds what is left is refused
+    with cstm.Server(ctx("hbm"), G, mem_budget=rings + 2 * est, lanes=1, builders=1) as srv:
         t = srv.submit(q.qlabel, q.qedges)
         res = srv.wait(t)
     assert res["status"] == cstm.ENOMEM and res["count"] == 0
@@ -97,3 +105,41 @@ def test_native_server_with_result_limits():
     say(f"limited: {serve.summarize(reqs)}")
     for r, p in zip(reqs, picks):
         assert r.error is None and r.count == min(expected[int(p)], lim)
+
+
+def test_native_server_on_the_16m_vertex_graph():
+    """The serving workload at full size (Chung-Lu, 16M vertices, 256M edges,
+    100 Zipf labels): Poisson arrivals drawn from the stored pool, each request
+    asking for min(#embeddings, 10^6); every served count equals the stored
+    oracle count and the count of the same query alone."""
+    import time
+
+    from paper_2102_10768_amd import cstm, serve
+
+    W = _load("c4")
+    lim = int(W["workload"]["queries"]["limit"])
+    t0 = time.time()
+    g = make_graph(W["workload"]["graph"], log=say)
+    assert g.m == W["graph_summary"]["m"]
+    say(f"c4 graph in {time.time() - t0:.0f}s")
+    G = gpu_graph(g, "hbm")
+    pool = [Query.from_dict(d) for d in W["queries"]]
+    expected = [int(d["count"]) for d in W["queries"]]
+    rng = np.random.Generator(np.random.PCG64(209))
+    picks = rng.integers(0, len(pool), size=80)
+    alone = {}
+    for i in sorted(set(int(p) for p in picks)):
+        cs = cstm.CST(ctx("hbm"), G, pool[i].qlabel, pool[i].qedges)
+        alone[i] = cs.count(limit=lim)
+        cs.close()
+        assert alone[i] == expected[i], f"pool query {i}"
+    arr = serve.poisson_arrivals(len(picks), 200.0, 210)
+    with cstm.Server(ctx("hbm"), G, mem_budget=64 << 30, lanes=2, builders=2, batch_wait_us=2000) as srv:
+        reqs = serve.replay_native(srv, arr, [pool[int(p)] for p in picks], limit=lim)
+        st = srv.stats()
+    say(f"c4 served: {serve.summarize(reqs)} stats {st}")
+    for r, p in zip(reqs, picks):
+        assert r.error is None, r.error
+        assert r.count == alone[int(p)] == expected[int(p)]
+    assert st["peak_bytes"] <= st["admission_bytes"]
+    G.close()

@@ -19,7 +19,7 @@ def test_oracle_and_generator_under_asan_and_ubsan(tmp_path):
     srcs = [os.path.join(ROOT, "tests", "sanitize_driver.c"), os.path.join(ROOT, "oracle", "oracle.c"),
             os.path.join(ROOT, "synth", "rmat_native.c")]
     subprocess.check_call(["gcc", "-O1", "-g", "-std=gnu11", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-                           "-fno-sanitize-recover=all", "-pthread", *srcs, "-o", str(exe)])
+                           "-fno-sanitize-recover=all", "-pthread", *srcs, "-o", str(exe), "-lm"])
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
     env.pop("LD_PRELOAD", None)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
