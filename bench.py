@@ -520,6 +520,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=2, help="--serve: enumeration lanes (streams)")
     ap.add_argument("--builders", type=int, default=2, help="--serve: CST builder threads (streams)")
     ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
+    ap.add_argument("--order-rule", type=int, default=1,
+                    help="--serve: matching order of the CSTs (cstm_tune.order_rule; 1, constraint-first, because "
+                         "under the path-based order one query of the 16M-vertex pool runs for more than 20 s)")
     ap.add_argument("--share", default="", help="comma-separated deltas: sweep the host-core share (Algorithm 3)")
     ap.add_argument("--host-threads", type=int, default=0, help="--share: host threads (0: the host's cores, <= 16)")
     ap.add_argument("--orders", type=int, default=0, help="matching-order study: random tree orders per query")
@@ -706,7 +709,7 @@ def serve_main(a, W, g, queries, expected):
 
     from paper_2102_10768_amd import cstm, serve
 
-    ctx = cstm.Context(0, tune={"collect_stats": 0})
+    ctx = cstm.Context(0, tune={"collect_stats": 0, "order_rule": a.order_rule})
     G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
                    torch.from_numpy(g.label).cuda())
     torch.cuda.synchronize()
@@ -745,7 +748,7 @@ def serve_main(a, W, g, queries, expected):
         s_srv["lane_overlap"] = sst["max_overlap"]
         s_srv["launches"] = sst["launches"]
         print(f"{qps} QPS served: {s_srv}", file=sys.stderr, flush=True)
-        plain = served if a.skip_plain else serve.run_sequential(backend, arr, qs, limit=limit)
+        plain = served if a.skip_plain else serve.run_sequential(backend, arr, qs, limit=limit, progress=say)
         s_pl = serve.summarize(plain)
         print(f"{qps} QPS plain: {s_pl}", file=sys.stderr, flush=True)
         bad = sum(r.count != w for r, w in zip(served, want)) + sum(r.count != w for r, w in zip(plain, want))
@@ -774,6 +777,7 @@ def serve_main(a, W, g, queries, expected):
                     f"builder threads, {a.lanes} enumeration lanes with batched persistent launches (batching window "
                     "under load); value is at the highest rate",
             "batch_wait_us": a.batch_wait_us,
+            "order_rule": a.order_rule,
             "query_pool": len(queries),
             "result_limit": limit,
             "mem_budget_bytes": budget,

@@ -211,7 +211,13 @@ cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out);
  * arrays, borrowed (kept alive by the caller until cstm_graph_free).
  * A device kernel checks the CSR; violations give CSTM_EINVAL.  The call also
  * builds the label index: vertices grouped by label, each group ordered by
- * degree descending then id ascending.  n must be < 2^31. */
+ * degree descending then id ascending, and a label-grouped copy of the rows
+ * (each neighbour's packed label/rank key, every row ordered by label then
+ * id; 4 bytes per entry, 8 when label and rank bits exceed 32), which CST
+ * construction reads.  Building the copy sorts about 2^28 row entries at a
+ * time (24 bytes of temporary device memory per entry); a chunk grows past
+ * that only by its last row, and one of 2^31 entries or more (a row of more
+ * than about 1.88 * 10^9 entries) gives CSTM_EINVAL.  n must be < 2^31. */
 cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                             const int32_t* col, const int32_t* label, int on_device, void* stream,
                             cstm_graph** out);
@@ -359,9 +365,11 @@ cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, i
  *
  * A request loop over one resident graph (the serving form of the method:
  * queries arrive one at a time and share the GPU).  The server admits
- * requests in arrival order while the device-memory bound of their CSTs
- * (cstm_cst_estimate, doubled for the block cache's rounding) fits
- * mem_budget; builds admitted CSTs on `builders` threads, each with its own
+ * requests in arrival order while the device-memory bound of their CST
+ * builds (cstm_cst_estimate, doubled for the block cache's rounding) fits
+ * mem_budget; once a CST is built its charge drops to twice the CST's own
+ * bytes (the build's temporaries are freed); builds admitted CSTs on
+ * `builders` threads, each with its own
  * stream; and gives every built CST to the next free enumeration lane, which
  * counts all CSTs built so far (up to max_batch) in one persistent launch on
  * its own stream, reading the CSTs from device memory whatever the context's

@@ -12,11 +12,13 @@
 //      non-tree candidate edges (stored once, from the earlier to the later
 //      endpoint in the order, which is the direction enumeration reads).
 // Membership of a data vertex w in C(u) is one range test on w's packed
-// (label, rank) key plus one lookup in a rank-indexed table.  The rows of a
+// (label, rank) key plus one lookup in a rank-indexed table.  G keeps a copy
+// of its rows with the neighbours' keys grouped by label, so for an edge
+// (u_p, u) only the run of each candidate's row that carries l(u) is read: a
+// binary search finds it, and the run is read in order.  The runs of a
 // parent's candidates are walked once per tree edge, in the top-down pass:
 // each entry's rank test is kept (`erank`), and the bottom-up test and both
-// passes over the tree list read it back in order instead of gathering keys
-// again.  Sizes stay on the device (kernels read them from a small table and
+// passes over the tree list read it back in order.  Sizes stay on the device (kernels read them from a small table and
 // run grids sized by host-side bounds from the label index), so a build waits
 // for the device four times: for the tree-list sizes, the path counts of the
 // order, the non-tree list sizes, and at the end.
@@ -40,18 +42,19 @@ __device__ inline int mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
-// Rows of a candidate array laid end to end: entry t of the flattened space is
-// entry t - rowoff[i] of the CSR row of candidate i, where rowoff is the
-// exclusive prefix sum of the candidates' degrees.  The number of candidates
-// lives on the device (*n), and rowoff[*n] is the number of entries.  Kernels
-// walk this space in tiles of kTile entries, one wavefront per tile, so a
-// hub's long row is shared by many wavefronts and short rows are packed
-// together.
+// The label runs of a candidate array's rows, for one label, laid end to
+// end: entry t of the flattened space is lkey[beg[i] + t - rowoff[i]], the
+// (t - rowoff[i])-th neighbour of candidate i with that label, where rowoff is
+// the exclusive prefix sum of the run lengths.  The number of candidates lives
+// on the device (*n), and rowoff[*n] is the number of entries.  Kernels walk
+// this space in tiles of kTile entries, one wavefront per tile, so a hub's
+// long run is shared by many wavefronts and short runs are packed together.
 constexpr int kTile = 512;
 
 struct Rows {
     const int32_t* cand;    // candidate data-vertex ids
-    const int64_t* rowoff;  // n + 1 prefix sums of their degrees
+    const int64_t* rowoff;  // n + 1 prefix sums of their run lengths
+    const int64_t* beg;     // n: where each candidate's run starts in lkey
     const int64_t* n;       // device: number of candidates
 };
 
@@ -82,29 +85,48 @@ __device__ inline void for_tiles(const Rows& R, F&& body) {
     }
 }
 
-__global__ void k_cand_degrees(const int32_t* __restrict__ cand, const int64_t* __restrict__ n_dev,
-                               const int64_t* __restrict__ row_ptr, int64_t* __restrict__ deg) {
+// The run of label l in each candidate's label-grouped row: its start and
+// length, by two binary searches over the row.
+template <class K>
+__global__ void k_seg(const int32_t* __restrict__ cand, const int64_t* __restrict__ n_dev,
+                      const int64_t* __restrict__ row_ptr, const K* __restrict__ lkey, int shift, uint64_t l,
+                      int64_t* __restrict__ len, int64_t* __restrict__ beg) {
     const int64_t n = *n_dev;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int32_t v = cand[i];
-        deg[i] = row_ptr[v + 1] - row_ptr[v];
+        int64_t lo = row_ptr[v], hi = row_ptr[v + 1];
+        const int64_t e = hi;
+        while (lo < hi) {  // first entry with label >= l
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if ((uint64_t)(lkey[mid] >> shift) < l) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t b = lo;
+        hi = e;
+        while (lo < hi) {  // first entry with label > l
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if ((uint64_t)(lkey[mid] >> shift) <= l) lo = mid + 1;
+            else hi = mid;
+        }
+        beg[i] = b;
+        len[i] = lo - b;
     }
 }
 
 // Top-down marking for a tree edge (u_p -> u): every neighbour of a parent
 // candidate that passes u's label/degree filter is marked in u's rank table,
-// and each entry's rank (or -1) is kept in erank for the later passes.
+// and each entry's rank (or -1) is kept in erank for the later passes.  R
+// holds the runs of label l(u), so only the degree filter (a rank below cnt0)
+// is left to test.
 template <class K>
-__global__ void k_mark(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                       const K* __restrict__ lkey, K base, int64_t cnt0, int32_t* __restrict__ mark,
+__global__ void k_mark(Rows R, const K* __restrict__ lkey, K base, int64_t cnt0, int32_t* __restrict__ mark,
                        int32_t* __restrict__ erank) {
     const int lane = lane_id();
     for_tiles(R, [&](int64_t, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
         for (int64_t t = t0 + lane; t < t1; t += CSTM_WAVE) {
             const int64_t i = owner_of(R.rowoff, lo, hi, t);
-            const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
-            const uint64_t d = (uint64_t)(K)(lkey[col[j]] - base);
+            const uint64_t d = (uint64_t)(K)(lkey[R.beg[i] + (t - R.rowoff[i])] - base);
             const bool hit = d < (uint64_t)cnt0;
             erank[t] = hit ? (int32_t)d : -1;
             if (hit) mark[d] = 1;
@@ -141,10 +163,12 @@ __global__ void k_iota_root(int32_t* __restrict__ loc, int64_t cnt0, const int32
 }
 
 // One tree child of the vertex being refined: the ranks its top-down pass
-// kept over the vertex's rows, and its (already refined) rank table.
+// kept over the vertex's runs of the child's label (offsets rowoff), and its
+// (already refined) rank table.
 struct ChildRef {
     const int32_t* erank;
     const int32_t* loc;
+    const int64_t* rowoff;
 };
 struct ChildSet {
     int32_t n;
@@ -152,15 +176,15 @@ struct ChildSet {
 };
 
 // Bottom-up validity: a candidate needs a neighbour in every refined child set.
-// One wavefront per candidate, reading the kept ranks of its row.
-__global__ void k_valid(Rows R, ChildSet ch, int32_t* __restrict__ flag) {
+// One wavefront per candidate, reading the kept ranks of its runs.
+__global__ void k_valid(const int64_t* __restrict__ n_dev, ChildSet ch, int32_t* __restrict__ flag) {
     const int lane = lane_id();
-    const int64_t n = *R.n;
+    const int64_t n = *n_dev;
     for (int64_t i = global_wave(); i < n; i += num_waves()) {
-        const int64_t b = R.rowoff[i], e = R.rowoff[i + 1];
         bool ok = true;
         for (int c = 0; c < ch.n && ok; ++c) {
             const ChildRef cr = ch.c[c];
+            const int64_t b = cr.rowoff[i], e = cr.rowoff[i + 1];
             bool found = false;
             for (int64_t j0 = b; j0 < e && !found; j0 += CSTM_WAVE) {
                 const int64_t j = j0 + lane;
@@ -243,7 +267,7 @@ __global__ void k_tree_count(Rows R, const int32_t* __restrict__ newidx, const i
     });
 }
 
-// Tree list entries, in G's row order (ascending data-vertex id), as indices
+// Tree list entries, in run order (ascending data-vertex id), as indices
 // into C(u): the hits of the flattened space are numbered in order, tile by
 // tile from tile_base, which lays the lists of consecutive owners end to end
 // exactly as the offsets from the per-owner counts do.
@@ -269,13 +293,12 @@ __global__ void k_tree_fill(Rows R, const int32_t* __restrict__ newidx, const in
     });
 }
 
-// Non-tree list (a -> b) sizes over a's rows: each entry's index in C(b) (or
-// -1) is kept in E for the fill, per refined owner counts go to cnt, per tile
-// counts to tile_cnt.
+// Non-tree list (a -> b) sizes over a's runs of label l(b): each entry's
+// index in C(b) (or -1) is kept in E for the fill, per refined owner counts go
+// to cnt, per tile counts to tile_cnt.
 template <class K>
-__global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const int64_t* __restrict__ row_ptr,
-                           const int32_t* __restrict__ col, const K* __restrict__ lkey, K base, int64_t cnt0,
-                           const int32_t* __restrict__ loc, int32_t* __restrict__ E,
+__global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const K* __restrict__ lkey, K base,
+                           int64_t cnt0, const int32_t* __restrict__ loc, int32_t* __restrict__ E,
                            unsigned long long* __restrict__ cnt, int64_t* __restrict__ tile_cnt) {
     const int lane = lane_id();
     for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
@@ -287,8 +310,7 @@ __global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const int
             const int32_t ni = newidx ? newidx[i] : (int32_t)i;
             int32_t idx = -1;
             if (in && ni >= 0) {
-                const int64_t j = row_ptr[R.cand[i]] + (t - R.rowoff[i]);
-                const uint64_t d = (uint64_t)(K)(lkey[col[j]] - base);
+                const uint64_t d = (uint64_t)(K)(lkey[R.beg[i] + (t - R.rowoff[i])] - base);
                 if (d < (uint64_t)cnt0) idx = loc[d];
             }
             if (in) E[t] = idx;
@@ -300,22 +322,21 @@ __global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const int
     });
 }
 
-// Non-tree list entries from E, with their data-vertex ids (ascending within
-// each list, since rows are sorted).
-__global__ void k_nt_fill(Rows R, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                          const int32_t* __restrict__ E, const int64_t* __restrict__ tile_base,
-                          int32_t* __restrict__ adj, int32_t* __restrict__ adj_gid) {
+// Non-tree list entries from E, with their data-vertex ids from C(b)
+// (ascending within each list, since runs keep the ids ascending).
+__global__ void k_nt_fill(Rows R, const int32_t* __restrict__ E, const int64_t* __restrict__ tile_base,
+                          const int32_t* __restrict__ cand_b, int32_t* __restrict__ adj,
+                          int32_t* __restrict__ adj_gid) {
     const int lane = lane_id();
-    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
+    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t, int64_t) {
         int64_t out = tile_base[tile];
         for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
             const int64_t t = s0 + lane;
             const int32_t idx = t < t1 ? E[t] : -1;
             const uint64_t m = ballot(idx >= 0);
             if (idx >= 0) {
-                const int64_t i = owner_of(R.rowoff, lo, hi, t);
                 adj[out + mbcnt(m)] = idx;
-                adj_gid[out + mbcnt(m)] = col[row_ptr[R.cand[i]] + (t - R.rowoff[i])];
+                adj_gid[out + mbcnt(m)] = cand_b[idx];
             }
             out += __popcll(m);
         }
@@ -476,10 +497,10 @@ unsigned tile_grid(int64_t bound) {
 
 int64_t tiles_of(int64_t bound) { return (bound + kTile - 1) / kTile + 1; }
 
-// The device size table of one build: per query vertex its top-down set size,
-// refined set size and row entries; per candidate list its entries.
-constexpr int kNsz = 0, kNfin = CSTM_MAX_K, kRtot = 2 * CSTM_MAX_K, kLent = 3 * CSTM_MAX_K;
-constexpr int kMetaSlots = 4 * CSTM_MAX_K + CSTM_MAX_NT;
+// The device size table of one build: per query vertex its top-down set size
+// and refined set size; per candidate list its entries.
+constexpr int kNsz = 0, kNfin = CSTM_MAX_K, kLent = 2 * CSTM_MAX_K;
+constexpr int kMetaSlots = 3 * CSTM_MAX_K + CSTM_MAX_NT;
 
 __global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
 
@@ -536,6 +557,8 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         rbound[u] = c->cnt0[u] ? g->deg_prefix[c->lb_lo[u] + c->cnt0[u]] - g->deg_prefix[c->lb_lo[u]] : 0;
     const bool k32 = g->key32 != nullptr;
     auto key_base = [&](int u) { return (uint64_t)q.qlabel[u] << g->key_shift; };
+    CSTM_REQUIRE(g->nnz == 0 || (k32 ? g->lkey32 != nullptr : g->lkey64 != nullptr), CSTM_EINVAL,
+                 "graph has no label-grouped rows");
 
     DevArena tmp;
     tmp.ctx = c->ctx;
@@ -558,16 +581,32 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     int32_t* tdrank[CSTM_MAX_K] = {};  // rank of each top-down candidate
     int32_t* cand_fin[CSTM_MAX_K] = {};  // refined set (top-down set for leaves)
     int32_t* newidx[CSTM_MAX_K] = {};  // top-down index -> refined index (nullptr: identity)
-    int64_t* rowoff[CSTM_MAX_K] = {};  // row offsets of the top-down set
-    int32_t* erank[CSTM_MAX_K] = {};   // by tree child: kept ranks over the parent's rows
-    auto rows_of = [&](int u) { return Rows{cand_td[u], rowoff[u], nsz(u)}; };
-    auto ensure_rows = [&](int u) {
-        if (rowoff[u]) return;
-        int64_t* deg = tmp.get_n<int64_t>(c->cnt0[u] + 1);
-        rowoff[u] = tmp.get_n<int64_t>(c->cnt0[u] + 1);
-        k_cand_degrees<<<cstm_blocks(c->cnt0[u], 256, 4096), 256, 0, s>>>(cand_td[u], nsz(u), g->row_ptr, deg);
+    int32_t* erank[CSTM_MAX_K] = {};   // by tree child: kept ranks over the parent's runs of its label
+    Rows trows[CSTM_MAX_K] = {};       // by tree child: the parent's top-down set, runs of the child's label
+    // runs of label l over u's top-down set, made once per (u, l)
+    struct RunsOf {
+        int u;
+        int32_t l;
+        Rows r;
+    };
+    std::vector<RunsOf> runs;
+    auto runs_of = [&](int u, int32_t l) -> Rows {
+        for (const RunsOf& x : runs)
+            if (x.u == u && x.l == l) return x.r;
+        const int64_t c0 = c->cnt0[u];
+        int64_t* len = tmp.get_n<int64_t>(c0 + 1);
+        int64_t* beg = tmp.get_n<int64_t>(c0 + 1);
+        int64_t* off = tmp.get_n<int64_t>(c0 + 1);
+        if (k32)
+            k_seg<uint32_t><<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(cand_td[u], nsz(u), g->row_ptr, g->lkey32,
+                                                                        g->key_shift, (uint64_t)l, len, beg);
+        else
+            k_seg<uint64_t><<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(cand_td[u], nsz(u), g->row_ptr, g->lkey64,
+                                                                        g->key_shift, (uint64_t)l, len, beg);
         HIP_TRY(hipGetLastError());
-        cstm_dscan_i64(deg, rowoff[u], nsz(u), c->cnt0[u], meta + kRtot + u, part, s);
+        cstm_dscan_i64(len, off, nsz(u), c0, nullptr, part, s);
+        runs.push_back({u, l, Rows{cand_td[u], off, beg, nsz(u)}});
+        return runs.back().r;
     };
 
     // tree lists: per child, the offsets over the refined parent set (bound-sized) and the tile bases
@@ -588,16 +627,16 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         for (int t = 1; t < k; ++t) {
             const int u = c->bfs[t], up = c->parent[u];
             const int64_t c0 = c->cnt0[u];
-            ensure_rows(up);
+            trows[u] = runs_of(up, q.qlabel[u]);
             loc[u] = tmp.get_n<int32_t>(c0);
             cstm_fill_words(loc[u], (size_t)c0 * 4, 0u, s);
             erank[u] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[up], 1));
             if (k32)
                 k_mark<uint32_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(
-                    rows_of(up), g->row_ptr, g->col, g->key32, (uint32_t)key_base(u), c0, loc[u], erank[u]);
+                    trows[u], g->lkey32, (uint32_t)key_base(u), c0, loc[u], erank[u]);
             else
-                k_mark<uint64_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(
-                    rows_of(up), g->row_ptr, g->col, g->key64, key_base(u), c0, loc[u], erank[u]);
+                k_mark<uint64_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(trows[u], g->lkey64, key_base(u), c0,
+                                                                               loc[u], erank[u]);
             HIP_TRY(hipGetLastError());
             int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
             cstm_dscan_i32(loc[u], scan, nullptr, c0, nsz(u), part, s);
@@ -612,7 +651,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             const int u = c->bfs[t];
             ChildSet ch{};
             for (int w = 0; w < k; ++w)
-                if (c->parent[w] == u) ch.c[ch.n++] = ChildRef{erank[w], loc[w]};
+                if (c->parent[w] == u) ch.c[ch.n++] = ChildRef{erank[w], loc[w], trows[w].rowoff};
             if (ch.n == 0) {
                 cand_fin[u] = cand_td[u];
                 k_copy_i64<<<1, 1, 0, s>>>(nsz(u), nfin(u));
@@ -621,7 +660,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             }
             const int64_t c0 = c->cnt0[u];
             int32_t* flag = tmp.get_n<int32_t>(c0 + 1);
-            k_valid<<<wave_grid(c0), kWaveBlock, 0, s>>>(rows_of(u), ch, flag);
+            k_valid<<<wave_grid(c0), kWaveBlock, 0, s>>>(nsz(u), ch, flag);
             HIP_TRY(hipGetLastError());
             int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
             cstm_dscan_i32(flag, scan, nsz(u), c0, nfin(u), part, s);
@@ -639,7 +678,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
             cstm_fill_words(cnt, (size_t)(c0p + 1) * 8, 0u, s);
             cstm_fill_words(tcnt, (size_t)(nt + 1) * 8, 0u, s);
-            k_tree_count<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(rows_of(p), newidx[p], erank[u], loc[u], cnt, tcnt);
+            k_tree_count<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], cnt, tcnt);
             HIP_TRY(hipGetLastError());
             toff_b[u] = tmp.get_n<int64_t>(c0p + 1);
             cstm_dscan_i64((const int64_t*)cnt, toff_b[u], nfin(p), c0p, meta + kLent + u, part, s);
@@ -675,7 +714,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             el.off = c->mem.get_n<int64_t>(c->ncand[p] + 1);
             HIP_TRY(hipMemcpyAsync(el.off, toff_b[u], (size_t)(c->ncand[p] + 1) * 8, hipMemcpyDeviceToDevice, s));
             el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-            k_tree_fill<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(rows_of(p), newidx[p], erank[u], loc[u], tbase[u],
+            k_tree_fill<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], tbase[u],
                                                                     el.adj);
             HIP_TRY(hipGetLastError());
             k_max_len<<<cstm_blocks(c->ncand[p], 256, 1024), 256, 0, s>>>(el.off, c->ncand[p], d_max + u);
@@ -779,6 +818,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     // 4c. non-tree candidate edges, earlier -> later in the order: sizes, one wait, fills
     std::vector<int32_t*> ntE(c->nontree.size(), nullptr);
     std::vector<int64_t*> ntbase(c->nontree.size(), nullptr);
+    std::vector<Rows> ntrows(c->nontree.size());
     for (size_t j = 0; j < c->nontree.size(); ++j) {
         int a = c->nontree[j].first, b = c->nontree[j].second;
         if (c->pos_of[a] > c->pos_of[b]) std::swap(a, b);
@@ -786,7 +826,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.from = c->pos_of[a];
         el.to = c->pos_of[b];
         if (!c->empty) {
-            ensure_rows(a);
+            ntrows[j] = runs_of(a, q.qlabel[b]);
             const int64_t nt = tiles_of(rbound[a]);
             unsigned long long* cnt = tmp.get_n<unsigned long long>(c->ncand[a] + 1);
             int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
@@ -795,12 +835,10 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             ntE[j] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[a], 1));
             if (k32)
                 k_nt_count<uint32_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
-                    rows_of(a), newidx[a], g->row_ptr, g->col, g->key32, (uint32_t)key_base(b), c->cnt0[b], loc[b],
-                    ntE[j], cnt, tcnt);
+                    ntrows[j], newidx[a], g->lkey32, (uint32_t)key_base(b), c->cnt0[b], loc[b], ntE[j], cnt, tcnt);
             else
                 k_nt_count<uint64_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
-                    rows_of(a), newidx[a], g->row_ptr, g->col, g->key64, key_base(b), c->cnt0[b], loc[b], ntE[j], cnt,
-                    tcnt);
+                    ntrows[j], newidx[a], g->lkey64, key_base(b), c->cnt0[b], loc[b], ntE[j], cnt, tcnt);
             HIP_TRY(hipGetLastError());
             el.off = c->mem.get_n<int64_t>(c->ncand[a] + 1);
             cstm_dscan_i64((const int64_t*)cnt, el.off, nullptr, c->ncand[a], meta + kLent + k + (int)j, part, s);
@@ -819,12 +857,12 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         HIP_TRY(hipStreamSynchronize(s));
         for (size_t j = 0; j < c->nontree.size(); ++j) {
             EdgeLists& el = c->nt[j];
-            int a = c->order[el.from];
+            const int a = c->order[el.from], b = c->order[el.to];
             el.entries = hm[kLent + k + (int)j];
             el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
             el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-            k_nt_fill<<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(rows_of(a), g->row_ptr, g->col, ntE[j], ntbase[j],
-                                                                  el.adj, el.adj_gid);
+            k_nt_fill<<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(ntrows[j], ntE[j], ntbase[j], c->cand[b], el.adj,
+                                                                  el.adj_gid);
             HIP_TRY(hipGetLastError());
         }
     }

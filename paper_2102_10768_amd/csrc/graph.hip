@@ -5,8 +5,12 @@
 // by label and orders each group by degree descending, then id ascending, so
 // that the label-and-degree candidate filter of a query vertex u
 // (l(v) = l(u), d(v) >= d_q(u)) is a prefix of u's label group, and a vertex's
-// rank inside its group decides membership in one comparison.  The index is
-// built with the library's own radix sort and scan (prims.hip).
+// rank inside its group decides membership in one comparison.  A second copy
+// of the rows holds each neighbour's packed key, with every row ordered by
+// (label, id): the neighbours of one label are then one run, found by binary
+// search, so CST construction reads only the run of the label it looks for.
+// The index and the copy are built with the library's own radix sort and scan
+// (prims.hip).
 #include <algorithm>
 
 #include "internal.h"
@@ -126,6 +130,60 @@ __global__ void k_ranks(const int32_t* __restrict__ perm, const int32_t* __restr
     }
 }
 
+// Label-grouped rows, built one chunk of rows at a time.  Sort key of row
+// entry j of row r: (r - r0, label of col[j]); the stable sort keeps the ids
+// ascending inside each (row, label) run.  One wavefront per row.
+template <class K>
+__global__ void k_regroup_keys(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                               const K* __restrict__ key, int key_shift, int64_t r0, int64_t r1, int64_t base,
+                               int label_bits, uint64_t* __restrict__ skey, int32_t* __restrict__ sval) {
+    const int lane = threadIdx.x & (CSTM_WAVE - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / CSTM_WAVE;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / CSTM_WAVE;
+    for (int64_t r = r0 + wave; r < r1; r += waves) {
+        const uint64_t hi = (uint64_t)(r - r0) << label_bits;
+        const int64_t e = row_ptr[r + 1];
+        for (int64_t j = row_ptr[r] + lane; j < e; j += CSTM_WAVE) {
+            skey[j - base] = hi | (uint64_t)(key[col[j]] >> key_shift);
+            sval[j - base] = (int32_t)(j - base);
+        }
+    }
+}
+
+// Entry i of the chunk's sorted order: the key of the neighbour it came from.
+template <class K>
+__global__ void k_regroup_gather(const int32_t* __restrict__ col, const K* __restrict__ key, int64_t base,
+                                 int64_t cnt, const int32_t* __restrict__ sval, K* __restrict__ lkey) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+        lkey[base + i] = key[col[base + sval[i]]];
+}
+
+// First row of every chunk: chunk c starts at the first row whose first entry
+// is at or after c * chunk (out[nchunks] = n); rowbase[c] = row_ptr[out[c]].
+__global__ void k_chunk_rows(const int64_t* __restrict__ row_ptr, int64_t n, int64_t chunk, int64_t nchunks,
+                             int64_t* __restrict__ out, int64_t* __restrict__ rowbase) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += stride) {
+        int64_t r = n;
+        if (c < nchunks) {
+            const int64_t t = c * chunk;
+            int64_t lo = 0, hi = n;
+            while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (row_ptr[mid] < t) lo = mid + 1;
+                else hi = mid;
+            }
+            r = lo;
+        }
+        out[c] = r;
+        rowbase[c] = row_ptr[r];
+    }
+}
+
+// Entries per radix sort of the regrouping (a longer row is sorted alone).
+constexpr int64_t kRegroupChunk = (int64_t)1 << 28;
+
 static int bits_for(uint64_t x) {  // bits needed to hold every value in [0, x]
     int b = 0;
     while (b < 64 && (x >> b) != 0) ++b;
@@ -150,6 +208,52 @@ __global__ void k_deg_at_least(const int64_t* __restrict__ row_ptr, const int32_
             else hi = mid;
         }
         out[t] = lo - base;
+    }
+}
+
+// The label-grouped copy of the rows (lkey32 or lkey64, allocated by the
+// caller): every row's neighbour keys ordered by (label, id).
+static void regroup_rows(cstm_graph* g, int label_bits, hipStream_t s) {
+    const int64_t n = g->n, nnz = g->nnz;
+    const int64_t nchunks = (nnz + kRegroupChunk - 1) / kRegroupChunk;
+    std::vector<int64_t> rows((size_t)nchunks + 1), base((size_t)nchunks + 1);
+    {
+        int64_t* d = g->mem.get_n<int64_t>(2 * ((size_t)nchunks + 1));
+        k_chunk_rows<<<cstm_blocks(nchunks + 1, 256, 64), 256, 0, s>>>(g->row_ptr, n, kRegroupChunk, nchunks, d,
+                                                                       d + nchunks + 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(rows.data(), d, ((size_t)nchunks + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(base.data(), d + nchunks + 1, ((size_t)nchunks + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        g->mem.release(d);
+    }
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int64_t r0 = rows[(size_t)c], r1 = rows[(size_t)c + 1];
+        const int64_t b = base[(size_t)c], cnt = base[(size_t)c + 1] - b;
+        if (r1 <= r0 || cnt <= 0) continue;
+        CSTM_REQUIRE(cnt < ((int64_t)1 << 31), CSTM_EINVAL, "a row of G is too long to regroup by label");
+        uint64_t* skey = g->mem.get_n<uint64_t>(cnt);
+        int32_t* sval = g->mem.get_n<int32_t>(cnt);
+        const unsigned grid = cstm_blocks((r1 - r0) * CSTM_WAVE, 256, 16384);
+        if (g->key32)
+            k_regroup_keys<uint32_t><<<grid, 256, 0, s>>>(g->row_ptr, g->col, g->key32, g->key_shift, r0, r1, b,
+                                                          label_bits, skey, sval);
+        else
+            k_regroup_keys<uint64_t><<<grid, 256, 0, s>>>(g->row_ptr, g->col, g->key64, g->key_shift, r0, r1, b,
+                                                          label_bits, skey, sval);
+        HIP_TRY(hipGetLastError());
+        if (label_bits > 0)  // one label: the rows are in order already
+            cstm_radix_sort_pairs(g->ctx, skey, sval, cnt, bits_for((uint64_t)(r1 - r0 - 1)) + label_bits, s);
+        if (g->key32)
+            k_regroup_gather<uint32_t><<<cstm_blocks(cnt, 256, 16384), 256, 0, s>>>(g->col, g->key32, b, cnt, sval,
+                                                                                   g->lkey32);
+        else
+            k_regroup_gather<uint64_t><<<cstm_blocks(cnt, 256, 16384), 256, 0, s>>>(g->col, g->key64, b, cnt, sval,
+                                                                                   g->lkey64);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        g->mem.release(skey);
+        g->mem.release(sval);
     }
 }
 
@@ -254,6 +358,11 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
                 k_ranks<uint64_t><<<cstm_blocks(n, 256, 16384), 256, 0, s>>>(g->perm, g->label, lp, n, 32, g->key64);
             }
             HIP_TRY(hipGetLastError());
+            if (nnz > 0) {
+                if (g->key32) g->lkey32 = g->mem.get_n<uint32_t>(nnz);
+                else g->lkey64 = g->mem.get_n<uint64_t>(nnz);
+                regroup_rows(g, label_bits, s);
+            }
             int64_t* dal = g->mem.get_n<int64_t>(g->deg_at_least.size());
             k_deg_at_least<<<cstm_blocks((int64_t)g->deg_at_least.size(), 256, 4096), 256, 0, s>>>(
                 g->row_ptr, g->perm, lp, L, dal);
@@ -307,24 +416,25 @@ extern "C" cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const i
             if ((uint64_t)c0[u] > max_c0) max_c0 = (uint64_t)c0[u];
             // kept: the candidate array; during the build: rank table, top-down
             // set and ranks, refined set, index map, flags and their scan (int32
-            // each), row degrees and offsets (int64 each)
-            bytes += 4ull * (uint64_t)c0[u] + (7ull * 4 + 2ull * 8) * ((uint64_t)c0[u] + 1);
+            // each)
+            bytes += 4ull * (uint64_t)c0[u] + 7ull * 4 * ((uint64_t)c0[u] + 1);
         }
         // path-count vectors of one leaf path
         bytes += 8ull * (uint64_t)k * (max_c0 + 1);
         // every candidate edge list: kept offsets over its owner and entries (ids
         // and, for non-tree lists, global ids); an edge (v, w) with v in C(a), w
         // in C(b) appears once, so either side's degree sum bounds the entries.
-        // During the build: per-owner counts and offsets (int64 each) and one
-        // int32 per row entry of the owner's candidates (kept ranks or indices),
-        // plus two int64 per tile of those rows.
+        // During the build: per-owner counts and offsets, and the owner's label
+        // runs (length, start, offset: int64 each), one int32 per run entry
+        // (kept ranks or indices; the owner's degree sum bounds the entries),
+        // plus two int64 per tile of those runs.
         for (int e = 0; e < m_q; ++e) {
             int a = qedges[2 * e], b = qedges[2 * e + 1];
             uint64_t ent = sdeg[a] < sdeg[b] ? sdeg[a] : sdeg[b];
             const uint64_t rows = sdeg[a] > sdeg[b] ? sdeg[a] : sdeg[b];
             const uint64_t cmax = (uint64_t)(c0[a] > c0[b] ? c0[a] : c0[b]);
             bytes += 8ull * (max_c0 + 1) + 8ull * ent;
-            bytes += 16ull * (cmax + 1) + 4ull * rows + 16ull * (rows / 512 + 2);
+            bytes += 40ull * (cmax + 1) + 4ull * rows + 16ull * (rows / 512 + 2);
         }
         *bytes_out = bytes + 65536;  // descriptor, size table, scan scratch and small flags
     });

@@ -122,6 +122,10 @@ struct cstm_graph {
     uint32_t* key32 = nullptr;
     uint64_t* key64 = nullptr;
     int key_shift = 32;
+    // label-grouped rows: lkey[row_ptr[v] + i] is the key of the i-th neighbour
+    // of v in (label, id) order; the same width as the keys (one is set)
+    uint32_t* lkey32 = nullptr;
+    uint64_t* lkey64 = nullptr;
     std::vector<int64_t> label_ptr;  // host, num_labels + 1
     // host: count of vertices of label l with degree >= d, d = 0..CSTM_MAX_K
     std::vector<int64_t> deg_at_least;

@@ -138,6 +138,13 @@ struct cstm_server {
             r->cst = c;
             r->built = true;
             r->res.built_s = now();
+            // the build's temporaries are back in the pool: from here on the
+            // request holds only its CST (doubled for the block cache's rounding)
+            const uint64_t kept = 2 * (c->bytes + sizeof(CstDev) + 65536) + 1;
+            if (kept < r->charge) {
+                in_use -= r->charge - kept;
+                r->charge = kept;
+            }
             ready.push_back(r);
             cv.notify_all();
         }

@@ -78,11 +78,12 @@ class CstmBackend:
         handle.close()
 
 
-def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):
+def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.perf_counter, progress=None):
     """Plain form: one request at a time in arrival order, build then count on one stream.
 
     ``arrivals`` are offsets in seconds from the start; ``limit`` > 0 asks for
-    min(total, limit); returns the requests."""
+    min(total, limit); ``progress`` (optional) is called with a line every
+    100 requests; returns the requests."""
     stream = backend.new_stream()
     start = clock()
     out = []
@@ -104,6 +105,8 @@ def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.per
         r.batch_size = 1
         r._event.set()
         out.append(r)
+        if progress and (rid + 1) % 100 == 0:
+            progress(f"plain form: {rid + 1} of {len(queries)} requests done")
     return out
 
 
