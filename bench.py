@@ -154,7 +154,8 @@ def say(*x):
 class Session:
     """One workload resident on the device, with the forms the benchmark times."""
 
-    def __init__(self, name: str, mode: str = "auto", build_streams: int = 4, max_queries: int = 0):
+    def __init__(self, name: str, mode: str = "auto", build_streams: int = 4, max_queries: int = 0,
+                 order_rule: int = 1):
         import torch
 
         from paper_2102_10768_amd import cstm
@@ -168,7 +169,7 @@ class Session:
         self.g = make_graph(self.W["workload"]["graph"], log=say)
         say(f"graph ready in {time.time() - t0:.1f}s: {self.g.summary()}")
         self.mode_id = {"auto": 0, "lds": 1, "hbm": 2}[mode]
-        self.ctx = cstm.Context(0, tune={"enum_mode": self.mode_id, "collect_stats": 0})
+        self.ctx = cstm.Context(0, tune={"enum_mode": self.mode_id, "collect_stats": 0, "order_rule": order_rule})
         self.stream = torch.cuda.current_stream()
         self.streams = [torch.cuda.Stream() for _ in range(max(1, build_streams))]
         g = self.g
@@ -261,7 +262,7 @@ def autotune_session(S, a):
 def headline(a):
     """The batched form of the main workload: the JSON line's value, roofline
     and CPU baseline, with the plain form on the same queries beside it."""
-    S = Session(a.workload, a.mode, a.build_streams, a.max_queries)
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
     total = sum(S.expected)
     bad = []
     tuned = autotune_session(S, a)
@@ -325,6 +326,7 @@ def headline(a):
             "form": f"batched: every CST built ({len(S.streams)} build streams), then one persistent launch "
                     "over a device task queue",
             "enum_mode": a.mode,
+            "order_rule": S.ctx.tune["order_rule"],
             "graph": {k: gs[k] for k in ("n", "m", "max_degree") if k in gs},
         },
         "parity": {"checked": len(S.expected), "mismatches": len(bad), "runs_checked": a.warmup + a.steps + 3},
@@ -438,7 +440,7 @@ def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> dict:
 def profile_launch(a):
     """One batched step of the workload (every CST built, one launch) with the
     given tuning and nothing else, for rocprofv3 runs; prints one JSON line."""
-    S = Session(a.workload, a.mode, a.build_streams, a.max_queries)
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
     if a.tune:
         S.ctx.tune = json.loads(a.tune)
     counts, st, tb, _ = S.batched_step()
@@ -454,7 +456,7 @@ def profile_launch(a):
 def extra_workload(a, name):
     """Plain and batched forms of another stored workload (and, for the
     power-law one, a short served-vs-plain comparison)."""
-    S = Session(name, a.mode, a.build_streams)
+    S = Session(name, a.mode, a.build_streams, order_rule=a.order_rule)
     total = sum(S.expected)
     bad = []
     counts = S.plain_step()
@@ -521,8 +523,9 @@ def main():
     ap.add_argument("--builders", type=int, default=2, help="--serve: CST builder threads (streams)")
     ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
     ap.add_argument("--order-rule", type=int, default=1,
-                    help="--serve: matching order of the CSTs (cstm_tune.order_rule; 1, constraint-first, because "
-                         "under the path-based order one query of the 16M-vertex pool runs for more than 20 s)")
+                    help="matching order the CSTs are built with first (cstm_tune.order_rule): 1, constraint-first, "
+                         "since under the path-based order (0) single random-walk queries of the hub-heavy graphs "
+                         "run for minutes; the autotuner of the batched form also times the other rule")
     ap.add_argument("--share", default="", help="comma-separated deltas: sweep the host-core share (Algorithm 3)")
     ap.add_argument("--host-threads", type=int, default=0, help="--share: host threads (0: the host's cores, <= 16)")
     ap.add_argument("--orders", type=int, default=0, help="matching-order study: random tree orders per query")

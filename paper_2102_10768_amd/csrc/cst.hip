@@ -489,10 +489,13 @@ struct EventTimer {
     }
 };
 
-// Grid of a tile walk over at most `bound` row entries (one wavefront per tile).
+// Grid of a tile walk over at most `bound` run entries: one wavefront per
+// tile, at most kMaxTileWaves (the walk is grid-strided, and the bound from the
+// label index is loose, so a larger grid would mostly launch idle waves).
+constexpr int64_t kMaxTileWaves = 8192;
 unsigned tile_grid(int64_t bound) {
     const int64_t tiles = (bound + kTile - 1) / kTile;
-    return wave_grid(tiles > 0 ? tiles : 1);
+    return wave_grid(tiles < 1 ? 1 : tiles < kMaxTileWaves ? tiles : kMaxTileWaves);
 }
 
 int64_t tiles_of(int64_t bound) { return (bound + kTile - 1) / kTile + 1; }
@@ -660,7 +663,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             }
             const int64_t c0 = c->cnt0[u];
             int32_t* flag = tmp.get_n<int32_t>(c0 + 1);
-            k_valid<<<wave_grid(c0), kWaveBlock, 0, s>>>(nsz(u), ch, flag);
+            k_valid<<<wave_grid(std::min<int64_t>(c0, kMaxTileWaves)), kWaveBlock, 0, s>>>(nsz(u), ch, flag);
             HIP_TRY(hipGetLastError());
             int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
             cstm_dscan_i32(flag, scan, nsz(u), c0, nfin(u), part, s);

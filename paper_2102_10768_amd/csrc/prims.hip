@@ -6,6 +6,7 @@
 // Scan: a fixed number of workgroups B, each owning one contiguous chunk of
 // the input.  Three launches: per-chunk sums, one workgroup scanning the B
 // sums, then every chunk scanned again from its base.  Sums are 64-bit.
+// Inputs of at most 8192 items are scanned by one workgroup in one launch.
 //
 // Sort: 8-bit digits, least significant first.  Every wavefront owns one
 // contiguous slice of the input; per pass it counts its digits, the
@@ -20,6 +21,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanMaxBlocks = 1024;
 constexpr int kScanItems = 4;  // items per thread per tile of the downsweep
+constexpr int64_t kScanSingleMax = 8192;  // up to this many items: one workgroup, one launch
 
 __device__ inline int lane_id() { return threadIdx.x & (CSTM_WAVE - 1); }
 
@@ -135,6 +137,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T* __restrict_
     }
 }
 
+// The whole scan in one workgroup, for short inputs: one launch instead of three.
+template <class T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_single(const T* __restrict__ in, T* __restrict__ out,
+                                                              const int64_t* __restrict__ n_dev, int64_t n_host,
+                                                              int64_t* __restrict__ total_out) {
+    __shared__ int64_t lds[kScanThreads / CSTM_WAVE];
+    const int64_t n = n_dev ? *n_dev : n_host;
+    int64_t carry = 0;
+    constexpr int64_t kTileItems = (int64_t)kScanThreads * kScanItems;
+    for (int64_t t0 = 0; t0 < n; t0 += kTileItems) {
+        const int64_t mine = t0 + (int64_t)threadIdx.x * kScanItems;
+        int64_t v[kScanItems];
+        int64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            v[j] = mine + j < n ? (int64_t)in[mine + j] : 0;
+            s += v[j];
+        }
+        int64_t tile_total = 0;
+        int64_t run = carry + block_excl_scan(s, lds, &tile_total);
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            if (mine + j < n) out[mine + j] = (T)run;
+            run += v[j];
+        }
+        carry += tile_total;
+    }
+    if (threadIdx.x == 0) {
+        out[n] = (T)carry;
+        if (total_out) *total_out = carry;
+    }
+}
+
 __global__ void k_fill_words(uint32_t* __restrict__ p, size_t n, uint32_t value) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
@@ -215,6 +250,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 template <class T>
 void scan_impl(const T* in, T* out, const int64_t* n_dev, int64_t n_host, int64_t n_bound, int64_t* total_out,
                int64_t* part, hipStream_t s) {
+    if (n_bound <= kScanSingleMax) {
+        k_scan_single<T><<<1, kScanThreads, 0, s>>>(in, out, n_dev, n_host, total_out);
+        HIP_TRY(hipGetLastError());
+        return;
+    }
     int64_t nb = (n_bound + 4095) / 4096;
     if (nb < 1) nb = 1;
     if (nb > kScanMaxBlocks) nb = kScanMaxBlocks;

@@ -5,7 +5,7 @@ of 12..32 vertices, each counting min(#embeddings, 10^9).
 The stored counts come from the CPU oracle (``tests/golden/make_workloads.py
 c5``); queries the oracle could not finish within its screen are INF there and
 are not run.  One session generates the graph (native generator), keeps it
-resident, builds every CST, and checks:
+resident, builds every CST (constraint-first matching order), and checks:
 
 * the batched form (one persistent launch over all CSTs, per-query limits)
   against every stored count;
@@ -55,7 +55,9 @@ def test_billion_edge_batch_matches_stored_oracle_counts():
     g = make_graph(W["workload"]["graph"], log=say)
     assert g.m == W["graph_summary"]["m"] and int(np.diff(g.row_ptr).max()) == W["graph_summary"]["max_degree"]
     say(f"graph generated in {time.time() - t0:.0f}s")
-    ctx = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 0})
+    # constraint-first order: under the path-based one single queries of this
+    # graph search for minutes (the order changes the work, not the counts)
+    ctx = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 0, "order_rule": 1})
     G = cstm.Graph(ctx, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
                    torch.from_numpy(g.label).cuda())
     torch.cuda.synchronize()
