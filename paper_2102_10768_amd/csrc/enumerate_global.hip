@@ -51,6 +51,8 @@ struct GQueue {
 // How often (s_memrealtime ticks, 100 MHz) a busy wavefront refreshes the
 // progress beat: 1 ms keeps the stores to that line rare.
 constexpr uint64_t kBeatTicks = 100000;
+// chunks between looks at the stop flag of a query with a count limit
+constexpr uint32_t kLimitCheck = 8;
 
 struct GArgs {
     const CstDev* descs;  // nq descriptors, contiguous
@@ -251,6 +253,24 @@ __device__ inline bool in_tree_list(const int32_t* tadj, const int32_t* gid, int
     return false;
 }
 
+// Entries of the tree-list range [lo, hi) of the last level that are not
+// among the earlier matches of its label (positions in `same`): the count of
+// its valid candidates when it closes no non-tree edge.  Those matches are
+// distinct, so each one found in the range removes exactly one entry.  The
+// match at position L is g_L, at d is g_d, at any other earlier position
+// lane jj of pg holds it.
+__device__ inline int64_t unused_in_list(const int32_t* tadj, const int32_t* gid, int64_t lo, int64_t hi,
+                                         uint32_t same, int d, int32_t g_d, int L, int32_t g_L, int32_t pg) {
+    int64_t n = hi - lo;
+    while (same) {
+        const int jj = __ffs(same) - 1;
+        same &= same - 1;
+        const int32_t x = jj == L ? g_L : (jj == d ? g_d : rl(pg, jj));
+        if (n > 0 && in_tree_list(tadj, gid, lo, hi, x)) --n;
+    }
+    return n;
+}
+
 // The candidates of level L for a partial result whose level-d entry is v
 // (d = L - 1) and whose earlier levels are in pl must lie in every list that
 // ends at L: the tree list of its parent's candidate and the non-tree list of
@@ -298,20 +318,39 @@ __device__ inline int64_t flat_total(const GArgs& A, const CstDev* D, int d, boo
     return wave_sum(len, A.small_lists);
 }
 
+// The embeddings the survivors of a chunk at the second-to-last level d
+// complete, when the last level closes no non-tree edge: per survivor its
+// tree-list length, less the earlier matches of the last level's label found
+// in that list (same), summed over the wavefront.
+__device__ inline int64_t last_total(const GArgs& A, const CstDev* D, int d, bool ok, int32_t v, int32_t g,
+                                     int32_t pl, int32_t pg, uint32_t same, int32_t my_par, const int64_t* my_toff,
+                                     const int32_t* my_tadj, const int32_t* my_gid, uint32_t my_nt, uint32_t my_ntf) {
+    int64_t len = 0;
+    if (ok) {
+        int64_t lo, hi;
+        pick_list(D, d + 1, d, v, pl, my_par, my_toff, my_nt, my_ntf, lo, hi);
+        len = same ? unused_in_list((const int32_t*)rlp(my_tadj, d + 1), (const int32_t*)rlp(my_gid, d + 1), lo, hi,
+                                    same, d, g, -1, 0, pg)
+                   : hi - lo;
+    }
+    return wave_sum(len, A.small_lists);
+}
+
 // Expand level L = d + 1 for every survivor (lanes with ok) of the current
 // level-d chunk at once, 64 (survivor, candidate) pairs per round, so short
 // lists do not leave lanes idle and no survivor needs a descent of its own.
 // L is either the last level (each passing pair is one embedding, written out
 // when listing) or, with sum_next, the second-to-last level of a query whose
-// last level has nothing to check (each passing pair adds the length of its
-// last-level list).  Returns the number of passing pairs.
+// last level closes no non-tree edge (each passing pair adds the length of
+// its last-level list, less the earlier matches of that level's label, the
+// positions in same_last, found in it).  Returns the number of passing pairs.
 __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D, int k, int d, bool ok, int32_t v,
                                                 int32_t g, int32_t pl, int32_t pg, int lane, int32_t my_par,
                                                 const int64_t* my_toff, const int32_t* my_tadj,
                                                 const int32_t* my_gid, uint32_t my_need, uint32_t my_same,
                                                 uint32_t my_nt, uint32_t my_ntf, uint32_t my_u, bool sum_next,
-                                                uint64_t& cnt, uint64_t& nN, uint64_t& nM, uint64_t& nS,
-                                                uint64_t& nC) {
+                                                uint32_t same_last, uint64_t& cnt, uint64_t& nN, uint64_t& nM,
+                                                uint64_t& nS, uint64_t& nC) {
     const int L = d + 1;
     const int pk = rl(my_par, L);
     const int64_t* toffL = (const int64_t*)rlp(my_toff, L);
@@ -322,6 +361,8 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
     // with sum_next: where the last level's list owner sits
     const int pK = sum_next ? rl(my_par, L + 1) : 0;
     const int64_t* toffK = sum_next ? (const int64_t*)rlp(my_toff, L + 1) : nullptr;
+    const int32_t* tadjK = sum_next && same_last ? (const int32_t*)rlp(my_tadj, L + 1) : nullptr;
+    const int32_t* gidK = sum_next && same_last ? (const int32_t*)rlp(my_gid, L + 1) : nullptr;
     int64_t b0 = 0;
     int32_t len = 0;  // the caller checked that the lengths sum to at most flat_max < 2^31
     int src = -1;     // the list each survivor reads (pick_list)
@@ -408,7 +449,9 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
             for (int r = 0; r < R; ++r) {
                 if (ok2[r]) {
                     const int32_t xk = pK == L ? v2[r] : (pK == d ? vs[r] : rl(pl, pK));
-                    lk += toffK[xk + 1] - toffK[xk];
+                    lk += same_last ? unused_in_list(tadjK, gidK, toffK[xk], toffK[xk + 1], same_last, d, gs[r], L,
+                                                     g2[r], pg)
+                                    : toffK[xk + 1] - toffK[xk];
                 }
             }
             lk = wave_sum(lk, A.small_lists);
@@ -444,7 +487,7 @@ __device__ __forceinline__ uint64_t flat_expand(const GArgs& A, const CstDev* D,
     return passed;
 }
 
-__global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
+__global__ __launch_bounds__(256, 4) void k_enumerate_global(GArgs A) {
     const int lane = lane_id();
     if (A.deadline) A.deadline += now_ticks();  // relative on entry, absolute from here on
     // per-query position records, held one per lane (lane d = position d)
@@ -455,6 +498,7 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
     int32_t my_par = -1;
     uint32_t my_same = 0, my_nt = 0, my_ntf = 0, my_u = 0, my_need = 0;
     bool sum_last = false;  // this query's last level is counted by list lengths
+    uint32_t same_last = 0;  // then: the earlier positions sharing its label
     const CstDev* D = nullptr;
     uint64_t cnt = 0, nN = 0, nM = 0, nF = 0, nS = 0, nC = 0, ntasks = 0, ndon = 0;
     uint64_t t_wait = 0, t_busy = 0;
@@ -479,6 +523,14 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
             continue;
         }
         int64_t lo = T->lo, hi = T->hi;
+        // with a count limit, an unpublished count of limit / 16384 or more is
+        // published at once (one chunk can add millions of summed embeddings),
+        // and the query's stop flag is read at least every kLimitCheck chunks:
+        // a late publication or a late look at the flag lets the query run far
+        // past its limit
+        const unsigned long long lim = A.limits ? A.limits[q] : 0ull;
+        const uint64_t publish_at = lim ? ((lim >> 14) ? (lim >> 14) : 1ull) : ~0ull;
+        const uint32_t check_cap = lim ? kLimitCheck : ~0u;
         int32_t pre = lane < CSTM_MAX_K ? T->prefix[lane] : 0;
         ++ntasks;
         if (q != cur_q) {
@@ -501,9 +553,10 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 my_u = (uint32_t)P.u;
                 my_need = (A.list || P.need_gid) ? 1u : 0u;
             }
-            // the last position has nothing to check when it shares no label with an
-            // earlier one and closes no non-tree edge: its tree list is all results
-            sum_last = A.last_sum > 0 && !A.list && k >= 2 && rl(my_same, k - 1) == 0 && rl(my_nt, k - 1) == 0;
+            // when the last position closes no non-tree edge its tree list holds all
+            // results but the earlier matches of its label, which a search finds
+            sum_last = A.last_sum > 0 && !A.list && k >= 2 && rl(my_nt, k - 1) == 0;
+            same_last = sum_last ? rl(my_same, k - 1) : 0u;
         }
         // level registers: lane d holds level d
         int32_t pl = lane < j ? pre : 0;
@@ -533,8 +586,11 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                     continue;
                 }
                 if (d == k - 1 && sum_last && d > 0) {
-                    // a donated remainder of an unconstrained last level
-                    const uint64_t n = (uint64_t)(end - cur);
+                    // a donated remainder of a last level counted by list lengths
+                    const uint64_t n =
+                        same_last ? (uint64_t)unused_in_list((const int32_t*)rlp(my_tadj, d), (const int32_t*)rlp(my_gid, d),
+                                                             cur, end, same_last, -1, 0, -1, 0, pg)
+                                  : (uint64_t)(end - cur);
                     cnt += n;
                     nN += n;
                     nS += n;
@@ -597,9 +653,11 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                         }
                     }
                 } else if (d == k - 2 && sum_last) {
-                    // unconstrained last level: every survivor adds its list length
+                    // last level counted by list lengths: every survivor adds its list
+                    // length, less the earlier matches of that level's label found in it
                     if (m) {
-                        const uint64_t n = (uint64_t)flat_total(A, D, d, ok, v, pl, my_par, my_toff, my_nt, my_ntf);
+                        const uint64_t n = (uint64_t)last_total(A, D, d, ok, v, g, pl, pg, same_last, my_par, my_toff,
+                                                                my_tadj, my_gid, my_nt, my_ntf);
                         cnt += n;
                         nN += n;
                         nS += n;
@@ -611,8 +669,8 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                     // level, or the second-to-last with the unconstrained last level summed
                     const bool sum_next = d == k - 3;
                     const uint64_t passed = flat_expand(A, D, k, d, ok, v, g, pl, pg, lane, my_par, my_toff, my_tadj,
-                                                        my_gid, my_need, my_same, my_nt, my_ntf, my_u, sum_next, cnt,
-                                                        nN, nM, nS, nC);
+                                                        my_gid, my_need, my_same, my_nt, my_ntf, my_u, sum_next,
+                                                        same_last, cnt, nN, nM, nS, nC);
                     nF += (uint64_t)__popcll(m) + (sum_next ? passed : 0);
                 } else if (m) {
                     M = m;
@@ -622,12 +680,11 @@ __global__ __launch_bounds__(256) void k_enumerate_global(GArgs A) {
                 // remainder of the shallowest open level when a consumer is waiting.
                 // The interval adapts: short while consumers wait (a narrow search
                 // spreads fast), doubling up to donate_period while none do.
-                if (++since_check >= period) {
+                if (++since_check >= (period < check_cap ? period : check_cap) || cnt >= publish_at) {
                     since_check = 0;
                     int want = 0, added = 0;
                     // with a count limit, publish the count found so far; once the
                     // query's count reaches its limit, every task of it stops
-                    const unsigned long long lim = A.limits ? A.limits[q] : 0ull;
                     const bool publish = lim && cnt;
                     if (lane == 0) {
                         const uint64_t now = now_ticks();

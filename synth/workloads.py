@@ -19,11 +19,16 @@ SMALL = {
 
 POWER_LAW_1M = {
     "name": "c2",
-    "title": "Chung-Lu 1M vertices, 16M edges, gamma 2.3, 32 Zipf(1.0) labels; screened 8-vertex random-walk queries",
+    "title": "Chung-Lu 1M vertices, 16M edges, gamma 2.3, 32 Zipf(1.0) labels; screened 8-vertex random-walk queries "
+             "(sparse: exact counts; dense: min(#embeddings, 10^9))",
     "graph": {"kind": "chung_lu", "n": 1_000_000, "m": 16_000_000, "gamma": 2.3, "seed": 12,
               "labels": {"kind": "zipf", "L": 32, "s": 1.0}},
-    # 50 sparse (average query degree < 3) and 50 dense (>= 3) random-walk queries
-    "queries": {"k": 8, "sparse": 50, "dense": 50, "seed": 22},
+    # 50 sparse (average query degree < 3) and 50 dense (>= 3) random-walk
+    # queries; a dense query counts min(#embeddings, dense_limit), since on this
+    # graph nearly every dense walk has more embeddings than an exact reference
+    # can enumerate
+    "queries": {"k": 8, "sparse": 50, "dense": 50, "seed": 22, "dense_limit": 1_000_000_000,
+                "dense_deadline_s": 120.0, "dense_budget": 15_000_000_000},
 }
 
 RMAT_22 = {

@@ -8,15 +8,17 @@ Expected values come from the CPU oracle (``oracle``); inputs come only
 from ``synth``.  For the sparse class of c2 the expected count is the exact
 labelled tree DP of ``closed_forms`` (see below).
 
-Screen (deterministic, host-independent): walks are drawn in order from the
+Screen (deterministic and host-independent but for the dense deadline): walks are drawn in order from the
 seeded query stream and join their class (sparse: average query degree below
 3, dense: 3 or more) while it has room.
   sparse: the query must be a tree with pairwise-distinct labels and have at
           most count_cap embeddings; its exact count is the labelled tree
           homomorphism DP (injectivity is automatic for such queries), a pin
           independent of the oracle that is exact at any graph size;
-  dense:  the oracle must finish it within node_budget visited partial
-          embeddings (at most dense_tries attempts).
+  dense:  the oracle must reach min(#embeddings, dense_limit) within the
+          workload's dense_budget visited partial embeddings and
+          dense_deadline_s seconds (at most dense_tries attempts); the stored
+          count is that minimum, and the query carries the limit.
 On the power-law graph almost every random-walk query has 10^9 to 10^25
 embeddings; the screen keeps the ones an exact reference can still count.
 """
@@ -78,6 +80,9 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
     exact = cf.ExactTreeCounter(g)
     spec = w["queries"]
     quota = {"sparse": int(spec["sparse"]), "dense": int(spec["dense"])}
+    dense_limit = int(spec.get("dense_limit", 0))
+    dense_deadline = float(spec.get("dense_deadline_s", 0.0))
+    dense_budget = int(spec.get("dense_budget", budget))
     got = {"sparse": [], "dense": []}
     rng = _rng(spec["seed"], STREAM_QUERIES)
     stats = {"draws": 0, "skipped_full": 0, "sparse_not_distinct_label_tree": 0, "sparse_over_cap": 0,
@@ -111,7 +116,8 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
                 continue
             stats["dense_tried"] += 1
             t = time.time()
-            r = oracle.match(g, q, node_budget=budget, threads=threads, lcol=lcol)
+            r = oracle.match(g, q, node_budget=dense_budget, deadline_s=dense_deadline, threads=threads, lcol=lcol,
+                             limit=dense_limit)
             dt = time.time() - t
             dense_spent += dt
             if r.status != oracle.OK:
@@ -119,6 +125,8 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
                 print(f"draw {draw} dense m_q={q.m_q} over budget ({dt:.1f}s)", flush=True)
                 continue
             d.update(draw=draw, kind=cls, count=r.count, nodes=r.nodes, oracle_s=round(dt, 3), expected_from="oracle")
+            if dense_limit:
+                d["limit"] = dense_limit
         got[cls].append(d)
         print(f"draw {draw} {cls} m_q={q.m_q} count={d['count']} "
               f"[{len(got['sparse'])}/{quota['sparse']} sparse, {len(got['dense'])}/{quota['dense']} dense]",
@@ -132,8 +140,10 @@ def make_screened(w: dict, budget: int, max_draws: int, threads: int, count_cap:
         "graph_summary": g.summary(),
         "screen": {"sparse_rule": "tree query with pairwise-distinct labels and at most count_cap embeddings "
                                   "(exact count: labelled tree homomorphism DP)",
-                   "dense_rule": "oracle (label-grouped rows) finishes within node_budget work units",
-                   "count_cap": count_cap, "node_budget": budget, "max_draws": max_draws,
+                   "dense_rule": "oracle (label-grouped rows) reaches min(total, dense_limit) within dense_budget "
+                                 "work units and dense_deadline_s seconds",
+                   "dense_limit": dense_limit, "dense_budget": dense_budget, "dense_deadline_s": dense_deadline,
+                   "count_cap": count_cap, "max_draws": max_draws,
                    "dense_tries": dense_tries, "dense_seconds_cap": dense_seconds,
                    "dense_oracle_seconds": round(dense_spent, 1), **stats,
                    "short": {c: quota[c] - len(got[c]) for c in quota}},

@@ -87,3 +87,20 @@ def test_workload_queries_skip_inf_and_carry_limits():
     assert exp == [3, 5] and lim == [7, 7] and inf == 1 and [q.k for q in qs] == [2, 1]
     qs, exp, lim, inf = b.workload_queries(W, max_queries=1)
     assert exp == [3] and inf == 1
+
+
+def test_cpu_baseline_samples_stored_queries_and_checks_finished_counts():
+    """The oracle baseline runs the stored queries of a small workload to their
+    stored counts (every one finishes here) and reports the rate it found."""
+    import types
+
+    b = _bench()
+    from synth import make_graph
+
+    W = b.load_workload("c1")
+    qs, exp, lim, _ = b.workload_queries(W)
+    S = types.SimpleNamespace(g=make_graph(W["workload"]["graph"]), queries=qs, limits=lim, expected=exp)
+    allc, one = b.cpu_baselines(S, types.SimpleNamespace(cpu_seconds=20.0), n_sample=4)
+    assert one["cores"] == 1 and allc["cores"] >= 1
+    for r in (allc, one):
+        assert r["value"] > 0 and r["kind"] == "oracle" and "4 finished" in r["sample"]
