@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from synth import Query, make_graph
-from gpu_common import ctx, gpu_graph
+from gpu_common import ctx, gpu_graph, gpu_graph_in
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,9 @@ def test_native_server_results_equal_results_alone(name, n_req, qps, wait_us):
     g = make_graph(W["workload"]["graph"])
     G = gpu_graph(g, "hbm")
     c = ctx("hbm")
-    pool = [Query.from_dict(d) for d in W["queries"]]
-    expected = [int(d["count"]) for d in W["queries"]]
+    exact = [d for d in W["queries"] if d.get("count") is not None and not d.get("limit")]
+    pool = [Query.from_dict(d) for d in exact]
+    expected = [int(d["count"]) for d in exact]
     rng = np.random.Generator(np.random.PCG64(205))
     if name == "c2":
         picks = rng.choice(np.argsort(expected)[: len(pool) // 2], size=n_req)
@@ -94,8 +95,9 @@ def test_native_server_with_result_limits():
     W = _load("c2")
     g = make_graph(W["workload"]["graph"])
     G = gpu_graph(g, "hbm")
-    pool = [Query.from_dict(d) for d in W["queries"]]
-    expected = [int(d["count"]) for d in W["queries"]]
+    exact = [d for d in W["queries"] if d.get("count") is not None and not d.get("limit")]
+    pool = [Query.from_dict(d) for d in exact]
+    expected = [int(d["count"]) for d in exact]
     rng = np.random.Generator(np.random.PCG64(207))
     picks = rng.integers(0, len(pool), size=60)
     arr = serve.poisson_arrivals(len(picks), 400.0, 208)
@@ -122,19 +124,22 @@ def test_native_server_on_the_16m_vertex_graph():
     g = make_graph(W["workload"]["graph"], log=say)
     assert g.m == W["graph_summary"]["m"]
     say(f"c4 graph in {time.time() - t0:.0f}s")
-    G = gpu_graph(g, "hbm")
+    # constraint-first order: under the path-based one a query of this pool
+    # searches for more than 20 s before it finds its 10^6 embeddings
+    c = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 0, "order_rule": 1})
+    G = gpu_graph_in(c, g)
     pool = [Query.from_dict(d) for d in W["queries"]]
     expected = [int(d["count"]) for d in W["queries"]]
     rng = np.random.Generator(np.random.PCG64(209))
     picks = rng.integers(0, len(pool), size=80)
     alone = {}
     for i in sorted(set(int(p) for p in picks)):
-        cs = cstm.CST(ctx("hbm"), G, pool[i].qlabel, pool[i].qedges)
+        cs = cstm.CST(c, G, pool[i].qlabel, pool[i].qedges)
         alone[i] = cs.count(limit=lim)
         cs.close()
         assert alone[i] == expected[i], f"pool query {i}"
     arr = serve.poisson_arrivals(len(picks), 200.0, 210)
-    with cstm.Server(ctx("hbm"), G, mem_budget=64 << 30, lanes=2, builders=2, batch_wait_us=2000) as srv:
+    with cstm.Server(c, G, mem_budget=64 << 30, lanes=2, builders=2, batch_wait_us=2000) as srv:
         reqs = serve.replay_native(srv, arr, [pool[int(p)] for p in picks], limit=lim)
         st = srv.stats()
     say(f"c4 served: {serve.summarize(reqs)} stats {st}")
@@ -143,3 +148,4 @@ def test_native_server_on_the_16m_vertex_graph():
         assert r.count == alone[int(p)] == expected[int(p)]
     assert st["peak_bytes"] <= st["admission_bytes"]
     G.close()
+    c.close()
