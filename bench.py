@@ -484,7 +484,8 @@ def extra_workload(a, name):
     if name == "c2" and a.served_requests > 0:
         S.ctx.tune = {"hbm_wgs_per_cu": 0, "hbm_donate_min": 0, "hbm_donate_period": 0, "hbm_flat_max": 0,
                       "hbm_donate_last_min": 0, "enum_mode": S.mode_id}
-        srow, bad_s = served_vs_plain(S.ctx, S.G, S.queries, S.expected, a.served_requests, a.served_qps, 201)
+        srow, bad_s = served_vs_plain(S.ctx, S.G, S.queries, S.expected, a.served_requests, a.served_qps, 201,
+                                      limit=S.limits)
         row["served"] = {"form": "cstm_server (2 builders, 2 lanes, batching window 2 ms) vs one at a time, "
                                  "same Poisson arrivals", **srow}
         row["parity"]["checked"] += 2 * a.served_requests
@@ -585,6 +586,8 @@ def served_vs_plain(ctx, G, queries, expected, n, qps, seed, limit=0, budget=64 
     picks = np.random.Generator(np.random.PCG64(seed + 100)).integers(0, len(queries), size=n)
     qs = [queries[int(p)] for p in picks]
     want = [expected[int(p)] for p in picks]
+    if not isinstance(limit, int):  # one limit per pool query
+        limit = [int(limit[int(p)]) for p in picks]
     with cstm.Server(ctx, G, mem_budget=budget, lanes=lanes, builders=builders, batch_wait_us=batch_wait_us) as srv:
         served = serve.replay_native(srv, arr, qs, limit=limit)
         sst = srv.stats()

@@ -78,12 +78,17 @@ class CstmBackend:
         handle.close()
 
 
-def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.perf_counter, progress=None):
+def _limit_of(limit, i: int) -> int:
+    """Result limit of request i: ``limit`` is one int for all, or one per request."""
+    return int(limit) if isinstance(limit, (int, np.integer)) else int(limit[i])
+
+
+def run_sequential(backend, arrivals, queries, *, limit=0, clock=time.perf_counter, progress=None):
     """Plain form: one request at a time in arrival order, build then count on one stream.
 
     ``arrivals`` are offsets in seconds from the start; ``limit`` > 0 asks for
-    min(total, limit); ``progress`` (optional) is called with a line every
-    100 requests; returns the requests."""
+    min(total, limit) (one int, or one per request); ``progress`` (optional)
+    is called with a line every 100 requests; returns the requests."""
     stream = backend.new_stream()
     start = clock()
     out = []
@@ -96,7 +101,8 @@ def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.per
         h = backend.build(q, stream)
         r.t_built = r.t_launch = clock()
         try:
-            r.count = int(backend.count_batch([h], stream, [limit] if limit else None)[0])
+            lim = _limit_of(limit, rid)
+            r.count = int(backend.count_batch([h], stream, [lim] if lim else None)[0])
         except Exception as e:
             r.error = f"enumeration failed: {e}"
         finally:
@@ -110,18 +116,18 @@ def run_sequential(backend, arrivals, queries, *, limit: int = 0, clock=time.per
     return out
 
 
-def replay_native(server, arrivals, queries, *, limit: int = 0, clock=time.perf_counter):
+def replay_native(server, arrivals, queries, *, limit=0, clock=time.perf_counter):
     """Submit ``queries[i]`` to a ``cstm.Server`` at ``arrivals[i]`` seconds after
-    the start (each with the result limit ``limit``, 0 = all), wait for every
-    result, and return them as ``Request`` records timed on the server's own
-    clock (submission to result)."""
+    the start (each with the result limit ``limit``, one int or one per
+    request, 0 = all), wait for every result, and return them as ``Request``
+    records timed on the server's own clock (submission to result)."""
     start = clock()
     tickets = []
-    for t, q in zip(arrivals, queries):
+    for i, (t, q) in enumerate(zip(arrivals, queries)):
         now = clock() - start
         if now < t:
             time.sleep(t - now)
-        tickets.append((server.submit(q.qlabel, q.qedges, limit), q))
+        tickets.append((server.submit(q.qlabel, q.qedges, _limit_of(limit, i)), q))
     out = []
     for rid, (tk, q) in enumerate(tickets):
         res = server.wait(tk)

@@ -52,6 +52,8 @@ class FakeBackend:
         time.sleep(max(h.seconds for h in handles))
         if any(h.count < 0 for h in handles):
             raise RuntimeError("device error")
+        if limits is not None:
+            return [min(h.count, lim) if lim else h.count for h, lim in zip(handles, limits)]
         return [h.count for h in handles]
 
     def release(self, h):
@@ -89,3 +91,14 @@ def test_poisson_arrivals_rate_and_seed():
     assert np.array_equal(a, b)
     assert np.all(np.diff(a) > 0)
     assert abs(len(a) / a[-1] - 200.0) < 6.0
+
+
+def test_sequential_form_takes_one_limit_or_one_per_request():
+    be = FakeBackend()
+    qs = _queries(12, 7)
+    arr = serve.poisson_arrivals(len(qs), 2000.0, 10)
+    lim = [0, 5, 10**10] * 4
+    reqs = serve.run_sequential(be, arr, qs, limit=lim)
+    assert [r.count for r in reqs] == [q.count if not m else min(q.count, m) for q, m in zip(qs, lim)]
+    reqs = serve.run_sequential(be, arr, qs, limit=3)
+    assert [r.count for r in reqs] == [min(q.count, 3) for q in qs]
