@@ -367,8 +367,9 @@ cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, i
  * queries arrive one at a time and share the GPU).  The server admits
  * requests in arrival order while the device-memory bound of their CST
  * builds (cstm_cst_estimate, doubled for the block cache's rounding) fits
- * mem_budget; once a CST is built its charge drops to twice the CST's own
- * bytes (the build's temporaries are freed); builds admitted CSTs on
+ * mem_budget; once a CST is built its charge drops to twice the device
+ * bytes the CST holds (the build's temporaries are freed); builds admitted
+ * CSTs on
  * `builders` threads, each with its own
  * stream; and gives every built CST to the next free enumeration lane, which
  * counts all CSTs built so far (up to max_batch) in one persistent launch on

@@ -112,6 +112,8 @@ void DevArena::release(void* p) {
             ctx->dfree(p);
             blocks[i] = blocks.back();
             blocks.pop_back();
+            sizes[i] = sizes.back();
+            sizes.pop_back();
             return;
         }
     }
@@ -121,6 +123,7 @@ void DevArena::clear() {
     if (!ctx) return;
     for (void* p : blocks) ctx->dfree(p);
     blocks.clear();
+    sizes.clear();
 }
 
 // ---------------------------------------------------------------- context API

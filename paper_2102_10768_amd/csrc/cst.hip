@@ -47,41 +47,111 @@ __device__ inline int mbcnt(uint64_t m) {
 // (t - rowoff[i])-th neighbour of candidate i with that label, where rowoff is
 // the exclusive prefix sum of the run lengths.  The number of candidates lives
 // on the device (*n), and rowoff[*n] is the number of entries.  Kernels walk
-// this space in tiles of kTile entries, one wavefront per tile, so a hub's
-// long run is shared by many wavefronts and short runs are packed together.
-constexpr int kTile = 512;
+// this space in parts: a part is at most kPartRounds rounds of 64 entries of
+// one block of 64 candidates (whose runs are contiguous).  A block of at most
+// 64 * kPartRounds entries is one part; a longer one (a hub's run) has
+// 1 + extra[b] parts, spread over the wavefronts, with exoff the exclusive
+// prefix of extra[] over the blocks (exoff[nblocks] = number of extra parts).
+// Part p of block b has the index b + exoff[b] + p, so parts are numbered in
+// the order of their entries.
+constexpr int kPartRounds = 8;
 
 struct Rows {
     const int32_t* cand;    // candidate data-vertex ids
     const int64_t* rowoff;  // n + 1 prefix sums of their run lengths
     const int64_t* beg;     // n: where each candidate's run starts in lkey
     const int64_t* n;       // device: number of candidates
+    const int64_t* exoff;   // nblocks + 1: prefix of the extra parts per block
 };
 
-// The candidate whose row holds flattened entry t: the last i in [lo, hi]
-// with rowoff[i] <= t (empty rows are skipped by construction).
-__device__ inline int64_t owner_of(const int64_t* __restrict__ rowoff, int64_t lo, int64_t hi, int64_t t) {
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (rowoff[mid] <= t) lo = mid;
-        else hi = mid - 1;
+constexpr int kWaveBlock = 256;  // threads per workgroup of the run walks
+
+__device__ inline int32_t wave_incl_max(int32_t x) {
+    const int lane = lane_id();
+    for (int o = 1; o < CSTM_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, CSTM_WAVE);
+        if (lane >= o && y > x) x = y;
     }
-    return lo;
+    return x;
 }
 
-// Walk every tile of the flattened rows; body(t0, t1, lo, hi) with the
-// tile's entry range and the range of candidates owning it.
-template <class F>
-__device__ inline void for_tiles(const Rows& R, F&& body) {
+// Extra parts of each block of 64 candidates (beyond its first) and, in
+// *nblocks, the number of blocks, for the scan that makes exoff.
+__global__ void k_extra_parts(const int64_t* __restrict__ rowoff, const int64_t* __restrict__ n_dev,
+                              int64_t* __restrict__ extra, int64_t* __restrict__ nblocks) {
+    const int64_t n = *n_dev;
+    const int64_t nb = (n + CSTM_WAVE - 1) / CSTM_WAVE;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (first == 0) *nblocks = nb;
+    for (int64_t b = first; b < nb; b += stride) {
+        const int64_t lo = b * CSTM_WAVE, hi = lo + CSTM_WAVE < n ? lo + CSTM_WAVE : n;
+        const int64_t rounds = (rowoff[hi] - rowoff[lo] + CSTM_WAVE - 1) / CSTM_WAVE;
+        const int64_t parts = (rounds + kPartRounds - 1) / kPartRounds;
+        extra[b] = parts > 1 ? parts - 1 : 0;
+    }
+}
+
+// Walk the runs part by part.  begin(item) and end(item) run once per part,
+// with the part's index; entry(valid, t, i, pos) runs on every lane of every
+// round, with the entry's flattened index t, its owner i and its position pos
+// in lkey (valid is false for the lanes past the block's last entry, whose t,
+// i and pos are not to be used but whose owner i is still a candidate of the
+// block).  The owner of an entry is the last lane whose non-empty run starts
+// at or before it: the run starts inside a round are marked (starts of
+// non-empty runs are distinct) and a prefix maximum carries them forward from
+// the owner of the entry before the round, which one ballot finds.  First
+// every block's first part (one wavefront per block), then the extra parts of
+// long blocks, each found by a binary search over exoff.
+template <class Begin, class Entry, class End>
+__device__ inline void for_blocks(const Rows& R, Begin&& begin, Entry&& entry, End&& end) {
+    __shared__ int32_t s_mark[kWaveBlock / CSTM_WAVE][CSTM_WAVE];
+    int32_t* mark = s_mark[threadIdx.x / CSTM_WAVE];
+    const int lane = lane_id();
     const int64_t n = *R.n;
-    if (n <= 0) return;
-    const int64_t total = R.rowoff[n];
-    const int64_t ntiles = (total + kTile - 1) / kTile;
-    for (int64_t tile = global_wave(); tile < ntiles; tile += num_waves()) {
-        const int64_t t0 = tile * kTile, t1 = t0 + kTile < total ? t0 + kTile : total;
-        const int64_t lo = owner_of(R.rowoff, 0, n - 1, t0);
-        const int64_t hi = owner_of(R.rowoff, lo, n - 1, t1 - 1);
-        body(tile, t0, t1, lo, hi);
+    const int64_t nblocks = (n + CSTM_WAVE - 1) / CSTM_WAVE;
+    auto part = [&](int64_t blk, int64_t p) {
+        const int64_t first = blk * CSTM_WAVE;
+        const int64_t last = first + CSTM_WAVE < n ? first + CSTM_WAVE : n;
+        const int64_t i = first + lane;
+        const bool has = i < last;
+        const int64_t r0 = R.rowoff[first];
+        const int64_t total = R.rowoff[last] - r0;
+        const int64_t start = has ? R.rowoff[i] - r0 : 0;
+        const int64_t len = has ? R.rowoff[i + 1] - r0 - start : 0;
+        const int64_t beg = has ? R.beg[i] : 0;
+        const int64_t item = blk + R.exoff[blk] + p;
+        const int64_t tb = p * (int64_t)kPartRounds * CSTM_WAVE;
+        const int64_t te = tb + (int64_t)kPartRounds * CSTM_WAVE < total ? tb + (int64_t)kPartRounds * CSTM_WAVE : total;
+        begin(item);
+        const uint64_t before = ballot(len > 0 && start < tb);
+        int32_t carry = before ? 63 - __clzll(before) : 0;  // owner lane of the entry before the part
+        for (int64_t t0 = tb; t0 < te; t0 += CSTM_WAVE) {
+            mark[lane] = -1;
+            __builtin_amdgcn_wave_barrier();
+            if (len > 0 && start >= t0 && start < t0 + CSTM_WAVE) mark[start - t0] = lane;
+            __builtin_amdgcn_wave_barrier();
+            const int32_t m = wave_incl_max(mark[lane]);
+            __builtin_amdgcn_wave_barrier();
+            const int32_t own = m > carry ? m : carry;
+            carry = __builtin_amdgcn_readlane(own, CSTM_WAVE - 1);
+            const int64_t tl = t0 + lane;
+            const int64_t ostart = __shfl(start, own);
+            const int64_t obeg = __shfl(beg, own);
+            entry(tl < te, r0 + tl, first + own, obeg + (tl - ostart));
+        }
+        end(item);
+    };
+    for (int64_t blk = global_wave(); blk < nblocks; blk += num_waves()) part(blk, 0);
+    const int64_t nextra = R.exoff[nblocks];
+    for (int64_t e = global_wave(); e < nextra; e += num_waves()) {
+        int64_t lo = 0, hi = nblocks - 1;  // the block b with exoff[b] <= e < exoff[b + 1]
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (R.exoff[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        part(lo, 1 + e - R.exoff[lo]);
     }
 }
 
@@ -122,16 +192,16 @@ __global__ void k_seg(const int32_t* __restrict__ cand, const int64_t* __restric
 template <class K>
 __global__ void k_mark(Rows R, const K* __restrict__ lkey, K base, int64_t cnt0, int32_t* __restrict__ mark,
                        int32_t* __restrict__ erank) {
-    const int lane = lane_id();
-    for_tiles(R, [&](int64_t, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
-        for (int64_t t = t0 + lane; t < t1; t += CSTM_WAVE) {
-            const int64_t i = owner_of(R.rowoff, lo, hi, t);
-            const uint64_t d = (uint64_t)(K)(lkey[R.beg[i] + (t - R.rowoff[i])] - base);
+    for_blocks(
+        R, [](int64_t) {},
+        [&](bool valid, int64_t t, int64_t, int64_t pos) {
+            if (!valid) return;
+            const uint64_t d = (uint64_t)(K)(lkey[pos] - base);
             const bool hit = d < (uint64_t)cnt0;
             erank[t] = hit ? (int32_t)d : -1;
             if (hit) mark[d] = 1;
-        }
-    });
+        },
+        [](int64_t) {});
 }
 
 // marks -> candidate indices: C(u) in rank order (degree desc, id asc); each
@@ -242,46 +312,43 @@ __device__ inline void add_runs(int64_t owner, int32_t ni, uint64_t hits, unsign
 
 // Tree list (u_p -> u) sizes from the kept ranks: an entry is in the list of
 // its (refined) owner when its rank survives in u's rank table.  Per refined
-// owner counts go to cnt (zeroed by the caller), per tile counts to tile_cnt.
+// owner counts go to cnt (zeroed by the caller), per block counts to tile_cnt.
 __global__ void k_tree_count(Rows R, const int32_t* __restrict__ newidx, const int32_t* __restrict__ erank,
                              const int32_t* __restrict__ loc, unsigned long long* __restrict__ cnt,
                              int64_t* __restrict__ tile_cnt) {
     const int lane = lane_id();
-    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
-        int64_t in_tile = 0;
-        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
-            const int64_t t = s0 + lane;
-            const bool in = t < t1;
-            const int64_t i = in ? owner_of(R.rowoff, lo, hi, t) : hi;
+    int64_t in_tile = 0;
+    for_blocks(
+        R, [&](int64_t) { in_tile = 0; },
+        [&](bool valid, int64_t t, int64_t i, int64_t) {
             const int32_t ni = newidx ? newidx[i] : (int32_t)i;
             bool hit = false;
-            if (in && ni >= 0) {
+            if (valid && ni >= 0) {
                 const int32_t r = erank[t];
                 hit = r >= 0 && loc[r] >= 0;
             }
             const uint64_t hits = ballot(hit);
             in_tile += __popcll(hits);
             add_runs(i, ni, hits, cnt);
-        }
-        if (lane == 0) tile_cnt[tile] = in_tile;
-    });
+        },
+        [&](int64_t blk) {
+            if (lane == 0) tile_cnt[blk] = in_tile;
+        });
 }
 
 // Tree list entries, in run order (ascending data-vertex id), as indices
-// into C(u): the hits of the flattened space are numbered in order, tile by
-// tile from tile_base, which lays the lists of consecutive owners end to end
+// into C(u): the hits of the flattened space are numbered in order, block by
+// block from tile_base, which lays the lists of consecutive owners end to end
 // exactly as the offsets from the per-owner counts do.
 __global__ void k_tree_fill(Rows R, const int32_t* __restrict__ newidx, const int32_t* __restrict__ erank,
                             const int32_t* __restrict__ loc, const int64_t* __restrict__ tile_base,
                             int32_t* __restrict__ adj) {
-    const int lane = lane_id();
-    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
-        int64_t out = tile_base[tile];
-        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
-            const int64_t t = s0 + lane;
+    int64_t out = 0;
+    for_blocks(
+        R, [&](int64_t blk) { out = tile_base[blk]; },
+        [&](bool valid, int64_t t, int64_t i, int64_t) {
             int32_t idx = -1;
-            if (t < t1) {
-                const int64_t i = owner_of(R.rowoff, lo, hi, t);
+            if (valid) {
                 const int32_t ni = newidx ? newidx[i] : (int32_t)i;
                 const int32_t r = erank[t];
                 if (ni >= 0 && r >= 0) idx = loc[r];
@@ -289,8 +356,8 @@ __global__ void k_tree_fill(Rows R, const int32_t* __restrict__ newidx, const in
             const uint64_t m = ballot(idx >= 0);
             if (idx >= 0) adj[out + mbcnt(m)] = idx;
             out += __popcll(m);
-        }
-    });
+        },
+        [](int64_t) {});
 }
 
 // Non-tree list (a -> b) sizes over a's runs of label l(b): each entry's
@@ -301,25 +368,24 @@ __global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const K* 
                            int64_t cnt0, const int32_t* __restrict__ loc, int32_t* __restrict__ E,
                            unsigned long long* __restrict__ cnt, int64_t* __restrict__ tile_cnt) {
     const int lane = lane_id();
-    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t lo, int64_t hi) {
-        int64_t in_tile = 0;
-        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
-            const int64_t t = s0 + lane;
-            const bool in = t < t1;
-            const int64_t i = in ? owner_of(R.rowoff, lo, hi, t) : hi;
+    int64_t in_tile = 0;
+    for_blocks(
+        R, [&](int64_t) { in_tile = 0; },
+        [&](bool valid, int64_t t, int64_t i, int64_t pos) {
             const int32_t ni = newidx ? newidx[i] : (int32_t)i;
             int32_t idx = -1;
-            if (in && ni >= 0) {
-                const uint64_t d = (uint64_t)(K)(lkey[R.beg[i] + (t - R.rowoff[i])] - base);
+            if (valid && ni >= 0) {
+                const uint64_t d = (uint64_t)(K)(lkey[pos] - base);
                 if (d < (uint64_t)cnt0) idx = loc[d];
             }
-            if (in) E[t] = idx;
+            if (valid) E[t] = idx;
             const uint64_t hits = ballot(idx >= 0);
             in_tile += __popcll(hits);
             add_runs(i, ni, hits, cnt);
-        }
-        if (lane == 0) tile_cnt[tile] = in_tile;
-    });
+        },
+        [&](int64_t blk) {
+            if (lane == 0) tile_cnt[blk] = in_tile;
+        });
 }
 
 // Non-tree list entries from E, with their data-vertex ids from C(b)
@@ -327,37 +393,20 @@ __global__ void k_nt_count(Rows R, const int32_t* __restrict__ newidx, const K* 
 __global__ void k_nt_fill(Rows R, const int32_t* __restrict__ E, const int64_t* __restrict__ tile_base,
                           const int32_t* __restrict__ cand_b, int32_t* __restrict__ adj,
                           int32_t* __restrict__ adj_gid) {
-    const int lane = lane_id();
-    for_tiles(R, [&](int64_t tile, int64_t t0, int64_t t1, int64_t, int64_t) {
-        int64_t out = tile_base[tile];
-        for (int64_t s0 = t0; s0 < t1; s0 += CSTM_WAVE) {
-            const int64_t t = s0 + lane;
-            const int32_t idx = t < t1 ? E[t] : -1;
+    int64_t out = 0;
+    for_blocks(
+        R, [&](int64_t blk) { out = tile_base[blk]; },
+        [&](bool valid, int64_t t, int64_t, int64_t) {
+            const int32_t idx = valid ? E[t] : -1;
             const uint64_t m = ballot(idx >= 0);
             if (idx >= 0) {
                 adj[out + mbcnt(m)] = idx;
                 adj_gid[out + mbcnt(m)] = cand_b[idx];
             }
             out += __popcll(m);
-        }
-    });
+        },
+        [](int64_t) {});
 }
-
-// Largest list length, from the list offsets.
-__global__ void k_max_len(const int64_t* __restrict__ off, int64_t n, int* __restrict__ max_len) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int m = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int64_t len = off[i + 1] - off[i];
-        m = len > m ? (int)len : m;
-    }
-    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) {
-        const int y = __shfl_xor(m, o, CSTM_WAVE);
-        m = y > m ? y : m;
-    }
-    if (lane_id() == 0 && m) atomicMax(max_len, m);
-}
-
 
 __device__ inline uint64_t sat_add(uint64_t a, uint64_t b) {
     uint64_t s = a + b;
@@ -423,8 +472,6 @@ __global__ void k_fill_ones(uint64_t* __restrict__ x, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 1;
 }
 
-constexpr int kWaveBlock = 256;
-
 unsigned wave_grid(int64_t items) {
     // one wave per item, at most a few passes per wave
     return cstm_blocks(items * CSTM_WAVE, kWaveBlock, 1u << 16);
@@ -489,16 +536,25 @@ struct EventTimer {
     }
 };
 
-// Grid of a tile walk over at most `bound` run entries: one wavefront per
-// tile, at most kMaxTileWaves (the walk is grid-strided, and the bound from the
-// label index is loose, so a larger grid would mostly launch idle waves).
-constexpr int64_t kMaxTileWaves = 8192;
-unsigned tile_grid(int64_t bound) {
-    const int64_t tiles = (bound + kTile - 1) / kTile;
-    return wave_grid(tiles < 1 ? 1 : tiles < kMaxTileWaves ? tiles : kMaxTileWaves);
+// Grid of a run walk over at most `cands` candidates: one wavefront per block
+// of 64, at most kMaxWalkWaves (the walk is grid-strided, and the candidate
+// bound from the label index is loose, so a larger grid would mostly launch
+// idle waves).
+constexpr int64_t kMaxWalkWaves = 8192;
+unsigned walk_grid(int64_t cands) {
+    const int64_t blocks = (cands + CSTM_WAVE - 1) / CSTM_WAVE;
+    return wave_grid(blocks < 1 ? 1 : blocks < kMaxWalkWaves ? blocks : kMaxWalkWaves);
 }
 
-int64_t tiles_of(int64_t bound) { return (bound + kTile - 1) / kTile + 1; }
+// Blocks of 64 candidates among at most `cands` (plus one).
+int64_t blocks_of(int64_t cands) { return (cands + CSTM_WAVE - 1) / CSTM_WAVE + 1; }
+
+// Slots of a per-part count array over at most `cands` candidates whose runs
+// hold at most `entries` entries: a block's extra part covers a full part of
+// entries of that block.
+int64_t parts_of(int64_t cands, int64_t entries) {
+    return blocks_of(cands) + entries / ((int64_t)kPartRounds * CSTM_WAVE) + 1;
+}
 
 // The device size table of one build: per query vertex its top-down set size
 // and refined set size; per candidate list its entries.
@@ -608,7 +664,15 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
                                                                         g->key_shift, (uint64_t)l, len, beg);
         HIP_TRY(hipGetLastError());
         cstm_dscan_i64(len, off, nsz(u), c0, nullptr, part, s);
-        runs.push_back({u, l, Rows{cand_td[u], off, beg, nsz(u)}});
+        // extra parts of long blocks: len is free again, and the block count
+        // goes to the last size-table slot of this (u, l)
+        const int64_t nbb = blocks_of(c0);
+        int64_t* exoff = tmp.get_n<int64_t>(nbb + 1);
+        int64_t* nb_dev = tmp.get_n<int64_t>(1);
+        k_extra_parts<<<cstm_blocks(nbb, 256, 1024), 256, 0, s>>>(off, nsz(u), len, nb_dev);
+        HIP_TRY(hipGetLastError());
+        cstm_dscan_i64(len, exoff, nb_dev, nbb, nullptr, part, s);
+        runs.push_back({u, l, Rows{cand_td[u], off, beg, nsz(u), exoff}});
         return runs.back().r;
     };
 
@@ -617,9 +681,18 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     int64_t* tbase[CSTM_MAX_K] = {};
     if (!c->empty) {
         // 1. root candidates: the filtered prefix of the root's label group
+        // a leaf's top-down set is its final set and a refined set is final:
+        // both are made in the CST's own memory (bound-sized), so nothing is
+        // copied once the sizes are known
+        bool leaf[CSTM_MAX_K];
+        for (int u = 0; u < k; ++u) {
+            leaf[u] = true;
+            for (int w = 0; w < k; ++w) leaf[u] = leaf[u] && c->parent[w] != u;
+        }
+        auto td_mem = [&](int u) { return leaf[u] ? c->mem.get_n<int32_t>(c->cnt0[u]) : tmp.get_n<int32_t>(c->cnt0[u]); };
         const int64_t c0r = c->cnt0[root];
         loc[root] = tmp.get_n<int32_t>(c0r);
-        cand_td[root] = tmp.get_n<int32_t>(c0r);
+        cand_td[root] = td_mem(root);
         tdrank[root] = tmp.get_n<int32_t>(c0r);
         k_iota_root<<<cstm_blocks(c0r, 256, 4096), 256, 0, s>>>(loc[root], c0r, g->perm + c->lb_lo[root],
                                                                 cand_td[root], tdrank[root]);
@@ -635,15 +708,15 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             cstm_fill_words(loc[u], (size_t)c0 * 4, 0u, s);
             erank[u] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[up], 1));
             if (k32)
-                k_mark<uint32_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(
+                k_mark<uint32_t><<<walk_grid(c->cnt0[up]), kWaveBlock, 0, s>>>(
                     trows[u], g->lkey32, (uint32_t)key_base(u), c0, loc[u], erank[u]);
             else
-                k_mark<uint64_t><<<tile_grid(rbound[up]), kWaveBlock, 0, s>>>(trows[u], g->lkey64, key_base(u), c0,
+                k_mark<uint64_t><<<walk_grid(c->cnt0[up]), kWaveBlock, 0, s>>>(trows[u], g->lkey64, key_base(u), c0,
                                                                                loc[u], erank[u]);
             HIP_TRY(hipGetLastError());
             int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
             cstm_dscan_i32(loc[u], scan, nullptr, c0, nsz(u), part, s);
-            cand_td[u] = tmp.get_n<int32_t>(c0);
+            cand_td[u] = td_mem(u);
             tdrank[u] = tmp.get_n<int32_t>(c0);
             k_assign<<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(loc[u], scan, c0, g->perm + c->lb_lo[u], cand_td[u],
                                                                 tdrank[u]);
@@ -663,11 +736,11 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             }
             const int64_t c0 = c->cnt0[u];
             int32_t* flag = tmp.get_n<int32_t>(c0 + 1);
-            k_valid<<<wave_grid(std::min<int64_t>(c0, kMaxTileWaves)), kWaveBlock, 0, s>>>(nsz(u), ch, flag);
+            k_valid<<<wave_grid(std::min<int64_t>(c0, kMaxWalkWaves)), kWaveBlock, 0, s>>>(nsz(u), ch, flag);
             HIP_TRY(hipGetLastError());
             int32_t* scan = tmp.get_n<int32_t>(c0 + 1);
             cstm_dscan_i32(flag, scan, nsz(u), c0, nfin(u), part, s);
-            cand_fin[u] = tmp.get_n<int32_t>(c0);
+            cand_fin[u] = c->mem.get_n<int32_t>(c0);
             newidx[u] = tmp.get_n<int32_t>(c0);
             k_refine<<<cstm_blocks(c0, 256, 4096), 256, 0, s>>>(cand_td[u], tdrank[u], flag, scan, nsz(u), loc[u],
                                                                 cand_fin[u], newidx[u]);
@@ -676,15 +749,16 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         // 4a. tree list sizes (parent -> child), from the kept ranks
         for (int t = 1; t < k; ++t) {
             const int u = c->bfs[t], p = c->parent[u];
-            const int64_t c0p = c->cnt0[p], nt = tiles_of(rbound[p]);
-            unsigned long long* cnt = tmp.get_n<unsigned long long>(c0p + 1);
-            int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
-            cstm_fill_words(cnt, (size_t)(c0p + 1) * 8, 0u, s);
-            cstm_fill_words(tcnt, (size_t)(nt + 1) * 8, 0u, s);
-            k_tree_count<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], cnt, tcnt);
+            const int64_t c0p = c->cnt0[p], nt = parts_of(c0p, rbound[p]);
+            // per-owner and per-part counts, zeroed by one fill
+            unsigned long long* cnt = tmp.get_n<unsigned long long>(c0p + nt + 2);
+            int64_t* tcnt = (int64_t*)(cnt + c0p + 1);
+            cstm_fill_words(cnt, (size_t)(c0p + nt + 2) * 8, 0u, s);
+            k_tree_count<<<walk_grid(c->cnt0[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], cnt, tcnt);
             HIP_TRY(hipGetLastError());
-            toff_b[u] = tmp.get_n<int64_t>(c0p + 1);
-            cstm_dscan_i64((const int64_t*)cnt, toff_b[u], nfin(p), c0p, meta + kLent + u, part, s);
+            // the list offsets stay with the CST; the scan also finds the longest list
+            toff_b[u] = c->mem.get_n<int64_t>(c0p + 1);
+            cstm_dscan_i64((const int64_t*)cnt, toff_b[u], nfin(p), c0p, meta + kLent + u, part, s, d_max + u);
             tbase[u] = tmp.get_n<int64_t>(nt + 1);
             cstm_dscan_i64(tcnt, tbase[u], nullptr, nt, nullptr, part, s);
         }
@@ -703,24 +777,17 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             for (int u = 0; u < k; ++u) c->ncand[u] = 0;
     }
     if (!c->empty) {
-        // the kept arrays at their exact sizes
-        for (int u = 0; u < k; ++u) {
-            c->cand[u] = c->mem.get_n<int32_t>(c->ncand[u]);
-            HIP_TRY(hipMemcpyAsync(c->cand[u], cand_fin[u], (size_t)c->ncand[u] * 4, hipMemcpyDeviceToDevice, s));
-        }
+        for (int u = 0; u < k; ++u) c->cand[u] = cand_fin[u];
         for (int t = 1; t < k; ++t) {
             const int u = c->bfs[t], p = c->parent[u];
             EdgeLists& el = c->tree[u];
             el.from = -1;
             el.to = -1;
             el.entries = hm[kLent + u];
-            el.off = c->mem.get_n<int64_t>(c->ncand[p] + 1);
-            HIP_TRY(hipMemcpyAsync(el.off, toff_b[u], (size_t)(c->ncand[p] + 1) * 8, hipMemcpyDeviceToDevice, s));
+            el.off = toff_b[u];
             el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-            k_tree_fill<<<tile_grid(rbound[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], tbase[u],
+            k_tree_fill<<<walk_grid(c->cnt0[p]), kWaveBlock, 0, s>>>(trows[u], newidx[p], erank[u], loc[u], tbase[u],
                                                                     el.adj);
-            HIP_TRY(hipGetLastError());
-            k_max_len<<<cstm_blocks(c->ncand[p], 256, 1024), 256, 0, s>>>(el.off, c->ncand[p], d_max + u);
             HIP_TRY(hipGetLastError());
         }
     }
@@ -830,25 +897,23 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.to = c->pos_of[b];
         if (!c->empty) {
             ntrows[j] = runs_of(a, q.qlabel[b]);
-            const int64_t nt = tiles_of(rbound[a]);
-            unsigned long long* cnt = tmp.get_n<unsigned long long>(c->ncand[a] + 1);
-            int64_t* tcnt = tmp.get_n<int64_t>(nt + 1);
-            cstm_fill_words(cnt, (size_t)(c->ncand[a] + 1) * 8, 0u, s);
-            cstm_fill_words(tcnt, (size_t)(nt + 1) * 8, 0u, s);
+            const int64_t nt = parts_of(c->cnt0[a], rbound[a]);
+            unsigned long long* cnt = tmp.get_n<unsigned long long>(c->ncand[a] + nt + 2);
+            int64_t* tcnt = (int64_t*)(cnt + c->ncand[a] + 1);
+            cstm_fill_words(cnt, (size_t)(c->ncand[a] + nt + 2) * 8, 0u, s);
             ntE[j] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[a], 1));
             if (k32)
-                k_nt_count<uint32_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
+                k_nt_count<uint32_t><<<walk_grid(c->cnt0[a]), kWaveBlock, 0, s>>>(
                     ntrows[j], newidx[a], g->lkey32, (uint32_t)key_base(b), c->cnt0[b], loc[b], ntE[j], cnt, tcnt);
             else
-                k_nt_count<uint64_t><<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(
+                k_nt_count<uint64_t><<<walk_grid(c->cnt0[a]), kWaveBlock, 0, s>>>(
                     ntrows[j], newidx[a], g->lkey64, key_base(b), c->cnt0[b], loc[b], ntE[j], cnt, tcnt);
             HIP_TRY(hipGetLastError());
             el.off = c->mem.get_n<int64_t>(c->ncand[a] + 1);
-            cstm_dscan_i64((const int64_t*)cnt, el.off, nullptr, c->ncand[a], meta + kLent + k + (int)j, part, s);
+            cstm_dscan_i64((const int64_t*)cnt, el.off, nullptr, c->ncand[a], meta + kLent + k + (int)j, part, s,
+                           d_max + k + (int)j);
             ntbase[j] = tmp.get_n<int64_t>(nt + 1);
             cstm_dscan_i64(tcnt, ntbase[j], nullptr, nt, nullptr, part, s);
-            k_max_len<<<cstm_blocks(c->ncand[a], 256, 1024), 256, 0, s>>>(el.off, c->ncand[a], d_max + k + (int)j);
-            HIP_TRY(hipGetLastError());
         } else {
             el.off = nullptr;
         }
@@ -864,7 +929,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             el.entries = hm[kLent + k + (int)j];
             el.adj = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
             el.adj_gid = c->mem.get_n<int32_t>(el.entries ? el.entries : 1);
-            k_nt_fill<<<tile_grid(rbound[a]), kWaveBlock, 0, s>>>(ntrows[j], ntE[j], ntbase[j], c->cand[b], el.adj,
+            k_nt_fill<<<walk_grid(c->cnt0[a]), kWaveBlock, 0, s>>>(ntrows[j], ntE[j], ntbase[j], c->cand[b], el.adj,
                                                                   el.adj_gid);
             HIP_TRY(hipGetLastError());
         }
@@ -931,6 +996,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     }
     for (auto& el : c->nt) bytes += 8ull * (c->ncand[c->order[el.from]] + 1) + 8ull * el.entries;
     c->bytes = bytes;
+    c->mem_bytes = c->mem.used();
     HIP_TRY(hipStreamSynchronize(s));
 }
 

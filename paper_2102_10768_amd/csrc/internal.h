@@ -89,10 +89,18 @@ struct cstm_ctx {
 struct DevArena {
     cstm_ctx* ctx = nullptr;
     std::vector<void*> blocks;
+    std::vector<size_t> sizes;  // bytes requested for each block
     void* get(size_t bytes) {
         void* p = ctx->dmalloc(bytes ? bytes : 16);
         blocks.push_back(p);
+        sizes.push_back(bytes ? bytes : 16);
         return p;
+    }
+    // bytes requested by the blocks held now
+    uint64_t used() const {
+        uint64_t t = 0;
+        for (size_t b : sizes) t += b;
+        return t;
     }
     template <class T>
     T* get_n(size_t n) {
@@ -272,6 +280,7 @@ struct cstm_cst {
     int64_t n_parts = 0;
     uint64_t max_blob = 0;
     bool empty = false;  // some candidate set is empty: no embedding
+    uint64_t mem_bytes = 0;  // device bytes the CST's arena holds after the build (bound-sized arrays included)
     double t_build = 0, t_part = 0, t_enum = 0;
     bool has_workload = false;     // W_CST computed (on first use)
     uint64_t workload = 0;         // W_CST of the workload DP (Section V-C), saturating at 2^64 - 1
@@ -284,10 +293,12 @@ struct cstm_cst {
 // the total, where len = *n_dev when n_dev is given (n is then an upper bound
 // that sizes the launch) and len = n otherwise; *total_out (may be NULL) also
 // receives the total.  part: scratch of kScanPartSlots int64 (one scan at a
-// time per buffer).  Nothing waits for the device.
+// time per buffer).  max_out (cstm_dscan_i64, may be NULL): raised by atomic
+// maximum to the largest input (inputs below 2^31; the caller zeroes it).
+// Nothing waits for the device.
 constexpr int kScanPartSlots = 1025;
 void cstm_dscan_i64(const int64_t* in, int64_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,
-                    int64_t* part, hipStream_t s);
+                    int64_t* part, hipStream_t s, int* max_out = nullptr);
 void cstm_dscan_i32(const int32_t* in, int32_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,
                     int64_t* part, hipStream_t s);
 void cstm_dscan_u32(const uint32_t* in, uint32_t* out, int64_t n, int64_t* part, hipStream_t s);

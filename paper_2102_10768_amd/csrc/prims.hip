@@ -4,9 +4,10 @@
 // LSD radix sort of (key, value) pairs, and a word fill.
 //
 // Scan: a fixed number of workgroups B, each owning one contiguous chunk of
-// the input.  Three launches: per-chunk sums, one workgroup scanning the B
-// sums, then every chunk scanned again from its base.  Sums are 64-bit.
-// Inputs of at most 8192 items are scanned by one workgroup in one launch.
+// the input.  Two launches: per-chunk sums, then every chunk scanned again
+// from its base, which each workgroup sums from the chunk sums before it.
+// Sums are 64-bit.  Inputs of at most 8192 items are scanned by one workgroup
+// in one launch.  On request the scan also reports the largest input.
 //
 // Sort: 8-bit digits, least significant first.  Every wavefront owns one
 // contiguous slice of the input; per pass it counts its digits, the
@@ -65,57 +66,74 @@ __device__ inline void chunk_of(int64_t n, int nb, int b, int64_t& lo, int64_t& 
     if (lo > n) lo = n;
 }
 
+__device__ inline int64_t wave_max64(int64_t x) {
+    for (int o = CSTM_WAVE / 2; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(x, o, CSTM_WAVE);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Per-chunk sums into part[]; with max_out, the largest input also goes
+// there (atomic maximum; the caller zeroes it).
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T* __restrict__ in, const int64_t* __restrict__ n_dev,
-                                                              int64_t n_host, int64_t* __restrict__ part) {
+                                                              int64_t n_host, int64_t* __restrict__ part,
+                                                              int* __restrict__ max_out) {
     __shared__ int64_t lds[kScanThreads / CSTM_WAVE];
+    __shared__ int64_t ldm[kScanThreads / CSTM_WAVE];
     const int64_t n = n_dev ? *n_dev : n_host;
     int64_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
-    int64_t s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += (int64_t)in[i];
+    int64_t s = 0, mx = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads) {
+        const int64_t x = (int64_t)in[i];
+        s += x;
+        mx = x > mx ? x : mx;
+    }
     s = wave_sum64(s);
-    if (lane_id() == 0) lds[threadIdx.x / CSTM_WAVE] = s;
+    mx = wave_max64(mx);
+    if (lane_id() == 0) {
+        lds[threadIdx.x / CSTM_WAVE] = s;
+        ldm[threadIdx.x / CSTM_WAVE] = mx;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int i = 0; i < kScanThreads / CSTM_WAVE; ++i) t += lds[i];
+        int64_t t = 0, m = 0;
+        for (int i = 0; i < kScanThreads / CSTM_WAVE; ++i) {
+            t += lds[i];
+            m = ldm[i] > m ? ldm[i] : m;
+        }
         part[blockIdx.x] = t;
+        if (max_out && m > 0) atomicMax(max_out, (int)m);
     }
 }
 
-// One workgroup: exclusive scan of the nb chunk sums in place; part[nb] = total.
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int64_t* __restrict__ part, int nb, T* __restrict__ out,
-                                                             const int64_t* __restrict__ n_dev, int64_t n_host,
-                                                             int64_t* __restrict__ total_out) {
-    __shared__ int64_t lds[kScanThreads / CSTM_WAVE];
-    int64_t carry = 0;
-    for (int base = 0; base < nb; base += kScanThreads) {
-        const int i = base + threadIdx.x;
-        const int64_t x = i < nb ? part[i] : 0;
-        int64_t tile_total = 0;
-        const int64_t ex = block_excl_scan(x, lds, &tile_total);
-        if (i < nb) part[i] = carry + ex;
-        carry += tile_total;
-    }
-    if (threadIdx.x == 0) {
-        part[nb] = carry;
-        const int64_t n = n_dev ? *n_dev : n_host;
-        out[n] = (T)carry;
-        if (total_out) *total_out = carry;
-    }
-}
-
+// Every chunk scanned from its base, the sum of the chunk sums before it
+// (each workgroup adds them up itself); the last workgroup writes the total
+// to out[n] and *total_out.
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T* __restrict__ in, T* __restrict__ out,
                                                             const int64_t* __restrict__ n_dev, int64_t n_host,
-                                                            const int64_t* __restrict__ part) {
+                                                            const int64_t* __restrict__ part,
+                                                            int64_t* __restrict__ total_out) {
     __shared__ int64_t lds[kScanThreads / CSTM_WAVE];
     const int64_t n = n_dev ? *n_dev : n_host;
     int64_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
-    int64_t carry = part[blockIdx.x];
+    int64_t before = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) before += part[i];
+    before = wave_sum64(before);
+    if (lane_id() == 0) lds[threadIdx.x / CSTM_WAVE] = before;
+    __syncthreads();
+    int64_t carry = 0;
+    for (int i = 0; i < kScanThreads / CSTM_WAVE; ++i) carry += lds[i];
+    __syncthreads();
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const int64_t total = carry + part[blockIdx.x];
+        out[n] = (T)total;
+        if (total_out) *total_out = total;
+    }
     constexpr int64_t kTileItems = (int64_t)kScanThreads * kScanItems;
     for (int64_t t0 = lo; t0 < hi; t0 += kTileItems) {
         const int64_t mine = t0 + (int64_t)threadIdx.x * kScanItems;
@@ -141,10 +159,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T* __restrict_
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_single(const T* __restrict__ in, T* __restrict__ out,
                                                               const int64_t* __restrict__ n_dev, int64_t n_host,
-                                                              int64_t* __restrict__ total_out) {
+                                                              int64_t* __restrict__ total_out, int* __restrict__ max_out) {
     __shared__ int64_t lds[kScanThreads / CSTM_WAVE];
     const int64_t n = n_dev ? *n_dev : n_host;
-    int64_t carry = 0;
+    int64_t carry = 0, mx = 0;
     constexpr int64_t kTileItems = (int64_t)kScanThreads * kScanItems;
     for (int64_t t0 = 0; t0 < n; t0 += kTileItems) {
         const int64_t mine = t0 + (int64_t)threadIdx.x * kScanItems;
@@ -154,6 +172,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_single(const T* __restric
         for (int j = 0; j < kScanItems; ++j) {
             v[j] = mine + j < n ? (int64_t)in[mine + j] : 0;
             s += v[j];
+            mx = v[j] > mx ? v[j] : mx;
         }
         int64_t tile_total = 0;
         int64_t run = carry + block_excl_scan(s, lds, &tile_total);
@@ -167,6 +186,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_single(const T* __restric
     if (threadIdx.x == 0) {
         out[n] = (T)carry;
         if (total_out) *total_out = carry;
+    }
+    if (max_out) {
+        mx = wave_max64(mx);
+        if (lane_id() == 0 && mx > 0) atomicMax(max_out, (int)mx);
     }
 }
 
@@ -249,28 +272,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 
 template <class T>
 void scan_impl(const T* in, T* out, const int64_t* n_dev, int64_t n_host, int64_t n_bound, int64_t* total_out,
-               int64_t* part, hipStream_t s) {
+               int64_t* part, hipStream_t s, int* max_out = nullptr) {
     if (n_bound <= kScanSingleMax) {
-        k_scan_single<T><<<1, kScanThreads, 0, s>>>(in, out, n_dev, n_host, total_out);
+        k_scan_single<T><<<1, kScanThreads, 0, s>>>(in, out, n_dev, n_host, total_out, max_out);
         HIP_TRY(hipGetLastError());
         return;
     }
     int64_t nb = (n_bound + 4095) / 4096;
     if (nb < 1) nb = 1;
     if (nb > kScanMaxBlocks) nb = kScanMaxBlocks;
-    k_scan_reduce<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n_dev, n_host, part);
+    k_scan_reduce<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n_dev, n_host, part, max_out);
     HIP_TRY(hipGetLastError());
-    k_scan_parts<T><<<1, kScanThreads, 0, s>>>(part, (int)nb, out, n_dev, n_host, total_out);
-    HIP_TRY(hipGetLastError());
-    k_scan_down<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n_dev, n_host, part);
+    k_scan_down<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n_dev, n_host, part, total_out);
     HIP_TRY(hipGetLastError());
 }
 
 }  // namespace
 
 void cstm_dscan_i64(const int64_t* in, int64_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,
-                    int64_t* part, hipStream_t s) {
-    scan_impl<int64_t>(in, out, n_dev, n_dev ? 0 : n, n, total_out, part, s);
+                    int64_t* part, hipStream_t s, int* max_out) {
+    scan_impl<int64_t>(in, out, n_dev, n_dev ? 0 : n, n, total_out, part, s, max_out);
 }
 
 void cstm_dscan_i32(const int32_t* in, int32_t* out, const int64_t* n_dev, int64_t n, int64_t* total_out,

@@ -139,8 +139,9 @@ struct cstm_server {
             r->built = true;
             r->res.built_s = now();
             // the build's temporaries are back in the pool: from here on the
-            // request holds only its CST (doubled for the block cache's rounding)
-            const uint64_t kept = 2 * (c->bytes + sizeof(CstDev) + 65536) + 1;
+            // request holds only its CST's arena (doubled for the block
+            // cache's rounding)
+            const uint64_t kept = 2 * (std::max(c->bytes, c->mem_bytes) + sizeof(CstDev) + 65536) + 1;
             if (kept < r->charge) {
                 in_use -= r->charge - kept;
                 r->charge = kept;
