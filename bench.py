@@ -504,7 +504,7 @@ def main():
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--extras", default="c2,c3", help="other stored workloads reported beside the main one")
     ap.add_argument("--mode", default="auto", choices=["auto", "hbm", "lds"])
-    ap.add_argument("--build-streams", type=int, default=4, help="streams (host threads) building CSTs in parallel")
+    ap.add_argument("--build-streams", type=int, default=8, help="streams (host threads) building CSTs in parallel")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)

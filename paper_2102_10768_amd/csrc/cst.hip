@@ -155,8 +155,9 @@ __device__ inline void for_blocks(const Rows& R, Begin&& begin, Entry&& entry, E
     }
 }
 
-// The run of label l in each candidate's label-grouped row: its start and
-// length, by two binary searches over the row.
+// The run of label l in each candidate's label-grouped row: its start by a
+// binary search over the row, its end by a galloping search from the start
+// (runs are mostly short, so the end is usually one or two probes away).
 template <class K>
 __global__ void k_seg(const int32_t* __restrict__ cand, const int64_t* __restrict__ n_dev,
                       const int64_t* __restrict__ row_ptr, const K* __restrict__ lkey, int shift, uint64_t l,
@@ -173,8 +174,24 @@ __global__ void k_seg(const int32_t* __restrict__ cand, const int64_t* __restric
             else hi = mid;
         }
         const int64_t b = lo;
-        hi = e;
-        while (lo < hi) {  // first entry with label > l
+        // first entry with label > l: nothing to find for an empty run; else
+        // probe b + 1, b + 3, b + 7, ... until one passes the run (or the row
+        // ends), then search the last gap
+        hi = b;
+        if (b < e && (uint64_t)(lkey[b] >> shift) == l) {
+            int64_t prev = b, step = 1;
+            for (;;) {
+                const int64_t nxt = prev + step;
+                if (nxt >= e || (uint64_t)(lkey[nxt] >> shift) > l) {
+                    lo = prev + 1;
+                    hi = nxt < e ? nxt : e;
+                    break;
+                }
+                prev = nxt;
+                step <<= 1;
+            }
+        }
+        while (lo < hi) {
             const int64_t mid = lo + ((hi - lo) >> 1);
             if ((uint64_t)(lkey[mid] >> shift) <= l) lo = mid + 1;
             else hi = mid;
