@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 LDS_PEAK_GBS = 128 * 256 * 2.4
 
 
-PROFILES = {"c2": "c2_power_law_hbm_counters.md", "c5": "c5_rmat26_hbm_counters.md"}
+PROFILES = {"c5": "c5_rmat26_hbm_counters.md"}
 
 
 def measured_traffic(workload: str):

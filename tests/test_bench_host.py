@@ -31,7 +31,7 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path):
     for d in ("profiles", os.path.join("paper_2102_10768_amd", "csrc")):
         os.makedirs(tmp_path / d)
     src = os.path.join("paper_2102_10768_amd", "csrc", "enumerate_global.hip")
-    prof = os.path.join("profiles", "c2_power_law_hbm_counters.md")
+    prof = os.path.join("profiles", "c5_rmat26_hbm_counters.md")
     shutil.copy(os.path.join(ROOT, src), tmp_path / src)
     shutil.copy(os.path.join(ROOT, prof), tmp_path / prof)
     b.ROOT = str(tmp_path)
@@ -39,16 +39,16 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path):
     for line in open(tmp_path / prof):
         if line.startswith("traffic_bytes_per_launch:"):
             want = float(line.split(":")[1])
-    cur = b.measured_traffic("c2")
+    cur = b.measured_traffic("c5")
     # the committed summary either matches the committed source (a number) or
     # is stale (None); a changed source must always give None
     assert cur in (want, None)
     assert b.measured_traffic("c3") is None
     with open(tmp_path / src, "a") as f:
         f.write("\n// changed\n")
-    assert b.measured_traffic("c2") is None
+    assert b.measured_traffic("c5") is None
     os.remove(tmp_path / prof)
-    assert b.measured_traffic("c2") is None
+    assert b.measured_traffic("c5") is None
 
 
 def _st(mode, ms, N=0, M=0, F=0, summed=0, image_bytes=0, launches=1):
