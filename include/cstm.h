@@ -225,6 +225,15 @@ void cstm_graph_free(cstm_graph* g);
 cstm_status cstm_graph_info(const cstm_graph* g, int64_t* n, int64_t* nnz, int32_t* num_labels,
                             int64_t* max_degree);
 
+/* Edges of G between each pair of labels, counted at load from the
+ * label-grouped rows: out[a * num_labels + b] (host array of cap entries) is
+ * the number of row entries (v, w) with l(v) = a and l(w) = b, so the table is
+ * symmetric and sums to nnz.  CST construction sizes its per-edge buffers and
+ * cstm_cst_estimate its bound with it.  *n_out (required) receives
+ * num_labels^2, or 0 when the table was not made (more than 128 labels, or no
+ * edges); at most cap entries are written. */
+cstm_status cstm_graph_label_edges(const cstm_graph* g, uint64_t* out, int64_t cap, int64_t* n_out);
+
 /* Build the CST of q (Section V-A, Algorithm 1) on the device.
  *   k in 1..32, qlabel[k] >= 0, qedges[2*m_q] (host arrays): undirected query
  *   edges as id pairs; q must be connected, with no self-loop or duplicate edge.

@@ -631,6 +631,12 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
     int64_t rbound[CSTM_MAX_K];
     for (int u = 0; u < k; ++u)
         rbound[u] = c->cnt0[u] ? g->deg_prefix[c->lb_lo[u] + c->cnt0[u]] - g->deg_prefix[c->lb_lo[u]] : 0;
+    // entries of the runs of label l(b) over a's candidates: a's degree sum,
+    // and the edges of G between the two labels
+    auto run_bound = [&](int a, int b) -> int64_t {
+        const uint64_t pb = g->pair_bound(q.qlabel[a], q.qlabel[b]);
+        return (uint64_t)rbound[a] < pb ? rbound[a] : (int64_t)pb;
+    };
     const bool k32 = g->key32 != nullptr;
     auto key_base = [&](int u) { return (uint64_t)q.qlabel[u] << g->key_shift; };
     CSTM_REQUIRE(g->nnz == 0 || (k32 ? g->lkey32 != nullptr : g->lkey64 != nullptr), CSTM_EINVAL,
@@ -723,7 +729,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
             trows[u] = runs_of(up, q.qlabel[u]);
             loc[u] = tmp.get_n<int32_t>(c0);
             cstm_fill_words(loc[u], (size_t)c0 * 4, 0u, s);
-            erank[u] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[up], 1));
+            erank[u] = tmp.get_n<int32_t>(std::max<int64_t>(run_bound(up, u), 1));
             if (k32)
                 k_mark<uint32_t><<<walk_grid(c->cnt0[up]), kWaveBlock, 0, s>>>(
                     trows[u], g->lkey32, (uint32_t)key_base(u), c0, loc[u], erank[u]);
@@ -766,7 +772,7 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         // 4a. tree list sizes (parent -> child), from the kept ranks
         for (int t = 1; t < k; ++t) {
             const int u = c->bfs[t], p = c->parent[u];
-            const int64_t c0p = c->cnt0[p], nt = parts_of(c0p, rbound[p]);
+            const int64_t c0p = c->cnt0[p], nt = parts_of(c0p, run_bound(p, u));
             // per-owner and per-part counts, zeroed by one fill
             unsigned long long* cnt = tmp.get_n<unsigned long long>(c0p + nt + 2);
             int64_t* tcnt = (int64_t*)(cnt + c0p + 1);
@@ -914,11 +920,11 @@ static void build_cst(cstm_cst* c, const QueryPrep& q) {
         el.to = c->pos_of[b];
         if (!c->empty) {
             ntrows[j] = runs_of(a, q.qlabel[b]);
-            const int64_t nt = parts_of(c->cnt0[a], rbound[a]);
+            const int64_t nt = parts_of(c->cnt0[a], run_bound(a, b));
             unsigned long long* cnt = tmp.get_n<unsigned long long>(c->ncand[a] + nt + 2);
             int64_t* tcnt = (int64_t*)(cnt + c->ncand[a] + 1);
             cstm_fill_words(cnt, (size_t)(c->ncand[a] + nt + 2) * 8, 0u, s);
-            ntE[j] = tmp.get_n<int32_t>(std::max<int64_t>(rbound[a], 1));
+            ntE[j] = tmp.get_n<int32_t>(std::max<int64_t>(run_bound(a, b), 1));
             if (k32)
                 k_nt_count<uint32_t><<<walk_grid(c->cnt0[a]), kWaveBlock, 0, s>>>(
                     ntrows[j], newidx[a], g->lkey32, (uint32_t)key_base(b), c->cnt0[b], loc[b], ntE[j], cnt, tcnt);

@@ -181,6 +181,33 @@ __global__ void k_chunk_rows(const int64_t* __restrict__ row_ptr, int64_t n, int
     }
 }
 
+// Edges of G between each pair of labels: pair[a * L + b] counts the row
+// entries (v, w) with l(v) = a and l(w) = b.  Each workgroup counts its rows
+// (one wavefront per row) in an L x L table in LDS, then adds it to the
+// global table.
+constexpr int kPairMaxLabels = 128;  // L x L 32-bit counters fit in 64 KiB of LDS
+template <class K>
+__global__ __launch_bounds__(256) void k_pair_counts(const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ label, const K* __restrict__ lkey,
+                                                     int key_shift, int64_t n, int L,
+                                                     unsigned long long* __restrict__ pair) {
+    __shared__ uint32_t h[kPairMaxLabels * kPairMaxLabels];
+    const int LL = L * L;
+    for (int i = threadIdx.x; i < LL; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (CSTM_WAVE - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / CSTM_WAVE;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / CSTM_WAVE;
+    for (int64_t v = wave; v < n; v += waves) {
+        const int base = label[v] * L;
+        const int64_t e = row_ptr[v + 1];
+        for (int64_t j = row_ptr[v] + lane; j < e; j += CSTM_WAVE) atomicAdd(&h[base + (int)(lkey[j] >> key_shift)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < LL; i += blockDim.x)
+        if (h[i]) atomicAdd(&pair[i], (unsigned long long)h[i]);
+}
+
 // Entries per radix sort of the regrouping (a longer row is sorted alone).
 constexpr int64_t kRegroupChunk = (int64_t)1 << 28;
 
@@ -382,6 +409,20 @@ extern "C" cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, co
             g->mem.release(dal);
             g->mem.release(ps);
             g->mem.release(part);
+            if (nnz > 0 && L <= kPairMaxLabels) {
+                unsigned long long* pc = g->mem.get_n<unsigned long long>((size_t)L * L);
+                cstm_fill_words(pc, (size_t)L * L * 8, 0u, s);
+                const unsigned grid = cstm_blocks(n * CSTM_WAVE, 256, 2048);
+                if (g->key32)
+                    k_pair_counts<uint32_t><<<grid, 256, 0, s>>>(g->row_ptr, g->label, g->lkey32, g->key_shift, n, L, pc);
+                else
+                    k_pair_counts<uint64_t><<<grid, 256, 0, s>>>(g->row_ptr, g->label, g->lkey64, g->key_shift, n, L, pc);
+                HIP_TRY(hipGetLastError());
+                g->pair_count.assign((size_t)L * L, 0);
+                HIP_TRY(hipMemcpyAsync(g->pair_count.data(), pc, (size_t)L * L * 8, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                g->mem.release(pc);
+            }
         }
         *out = g;
     });
@@ -426,12 +467,17 @@ extern "C" cstm_status cstm_cst_estimate(const cstm_graph* g, int32_t k, const i
         // in C(b) appears once, so either side's degree sum bounds the entries.
         // During the build: per-owner counts and offsets, and the owner's label
         // runs (length, start, offset: int64 each), one int32 per run entry
-        // (kept ranks or indices; the owner's degree sum bounds the entries),
-        // plus two int64 per tile of those runs.
+        // (kept ranks or indices; the owner's degree sum and the edges of G
+        // between the two labels bound the entries), plus two int64 per part
+        // of those runs.
         for (int e = 0; e < m_q; ++e) {
             int a = qedges[2 * e], b = qedges[2 * e + 1];
+            // the edges of G between the two labels bound both
+            const uint64_t pairs = g->pair_bound(qlabel[a], qlabel[b]);
             uint64_t ent = sdeg[a] < sdeg[b] ? sdeg[a] : sdeg[b];
-            const uint64_t rows = sdeg[a] > sdeg[b] ? sdeg[a] : sdeg[b];
+            ent = ent < pairs ? ent : pairs;
+            uint64_t rows = sdeg[a] > sdeg[b] ? sdeg[a] : sdeg[b];
+            rows = rows < pairs ? rows : pairs;
             const uint64_t cmax = (uint64_t)(c0[a] > c0[b] ? c0[a] : c0[b]);
             bytes += 8ull * (max_c0 + 1) + 8ull * ent;
             bytes += 40ull * (cmax + 1) + 4ull * rows + 16ull * (rows / 512 + 2);
@@ -455,5 +501,15 @@ extern "C" cstm_status cstm_graph_info(const cstm_graph* g, int64_t* n, int64_t*
         if (nnz) *nnz = g->nnz;
         if (num_labels) *num_labels = g->num_labels;
         if (max_degree) *max_degree = g->max_degree;
+    });
+}
+
+extern "C" cstm_status cstm_graph_label_edges(const cstm_graph* g, uint64_t* out, int64_t cap, int64_t* n_out) {
+    return cstm_guard([&] {
+        CSTM_REQUIRE(g && n_out, CSTM_EINVAL, "NULL argument");
+        CSTM_REQUIRE(cap >= 0 && (cap == 0 || out), CSTM_EINVAL, "bad output array");
+        const int64_t n = (int64_t)g->pair_count.size();
+        *n_out = n;
+        for (int64_t i = 0; i < n && i < cap; ++i) out[i] = g->pair_count[(size_t)i];
     });
 }

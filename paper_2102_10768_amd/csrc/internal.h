@@ -140,6 +140,17 @@ struct cstm_graph {
     // host: prefix sums of degrees in label-index order (n + 1 entries)
     std::vector<int64_t> deg_prefix;
 
+    // host: edges of G between each pair of labels (row entries (v, w) with
+    // l(v) = a, l(w) = b at a * num_labels + b); empty above 128 labels
+    std::vector<uint64_t> pair_count;
+
+    // An upper bound on the row entries from label-a vertices to label-b
+    // neighbours (~0 when unknown).
+    uint64_t pair_bound(int32_t a, int32_t b) const {
+        if (pair_count.empty() || a < 0 || b < 0 || a >= num_labels || b >= num_labels) return ~0ull;
+        return pair_count[(size_t)a * num_labels + b];
+    }
+
     int64_t count_ge(int32_t l, int32_t d) const {
         if (l < 0 || l >= num_labels) return 0;
         if (d > CSTM_MAX_K) d = CSTM_MAX_K;

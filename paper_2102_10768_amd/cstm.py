@@ -140,7 +140,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 EXPORTS = [
     "cstm_ctx_create", "cstm_ctx_destroy", "cstm_ctx_get_tune", "cstm_ctx_set_tune", "cstm_ctx_lds_bytes",
-    "cstm_graph_load", "cstm_graph_free", "cstm_graph_info",
+    "cstm_graph_load", "cstm_graph_free", "cstm_graph_info", "cstm_graph_label_edges",
     "cstm_cst_build", "cstm_cst_partition", "cstm_cst_info_get", "cstm_cst_candidates",
     "cstm_enumerate", "cstm_batch_enumerate", "cstm_cst_times", "cstm_cst_free",
     "cstm_last_error", "cstm_version", "cstm_ctx_last_enum_stats", "cstm_cst_estimate",
@@ -180,6 +180,7 @@ def load_library():
         "cstm_graph_load": (st, [P, I64, I64, P, P, P, ctypes.c_int, P, ctypes.POINTER(P)]),
         "cstm_graph_free": (None, [P]),
         "cstm_graph_info": (st, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I64)]),
+        "cstm_graph_label_edges": (st, [P, P, I64, ctypes.POINTER(I64)]),
         "cstm_cst_build": (st, [P, P, I32, P, I32, P, P, ctypes.POINTER(P)]),
         "cstm_cst_partition": (st, [P, U64, I32, U64, ctypes.POINTER(I64)]),
         "cstm_cst_info_get": (st, [P, ctypes.POINTER(cstm_cst_info)]),
@@ -363,6 +364,17 @@ class Graph:
         _check(load_library().cstm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(L),
                                               ctypes.byref(md)))
         return {"n": n.value, "nnz": nnz.value, "num_labels": L.value, "max_degree": md.value}
+
+    def label_edges(self):
+        """(L, L) uint64 array of edges between label pairs, or None when not made."""
+        n = ctypes.c_int64()
+        _check(load_library().cstm_graph_label_edges(self.handle, None, 0, ctypes.byref(n)))
+        if n.value == 0:
+            return None
+        out = np.zeros(n.value, dtype=np.uint64)
+        _check(load_library().cstm_graph_label_edges(self.handle, out.ctypes.data, n.value, ctypes.byref(n)))
+        L = int(round(n.value ** 0.5))
+        return out.reshape(L, L)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -425,3 +425,30 @@ def test_constraint_first_order_rule_keeps_every_embedding():
         cs.close()
         Gt.close()
     c.close()
+
+
+def test_label_edge_table_matches_the_csr():
+    """The per-graph count of edges between label pairs (which bounds the
+    construction buffers) equals a count made directly from the CSR; above 128
+    labels no table is made."""
+    from synth.graphs import Graph, erdos_renyi, uniform_labels, zipf_labels
+
+    graphs = [_c1()]
+    for seed, L in ((51, 1), (52, 7), (53, 128), (54, 129)):
+        row_ptr, col = erdos_renyi(600, 0.02, seed)
+        lab = uniform_labels(600, L, seed) if L != 7 else zipf_labels(600, L, 1.0, seed)
+        lab[0] = L - 1  # the largest label occurs
+        graphs.append(Graph(600, row_ptr, col, lab, f"er{L}"))
+    for g in graphs:
+        G = gpu_graph(g)
+        L = int(g.label.max()) + 1
+        t = G.label_edges()
+        say(f"{g.name}: L={L}, table {'none' if t is None else t.shape}")
+        if L > 128:
+            assert t is None
+            continue
+        src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        want = np.zeros((L, L), dtype=np.uint64)
+        np.add.at(want, (g.label[src], g.label[g.col]), 1)
+        assert t.shape == (L, L) and np.array_equal(t, want)
+        assert int(t.sum()) == int(g.row_ptr[-1])
