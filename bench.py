@@ -519,7 +519,7 @@ def main():
     ap.add_argument("--mem-budget-gb", type=float, default=0.0, help="admission budget for --serve (default: the workload's)")
     ap.add_argument("--batch-wait-us", type=int, default=2000, help="--serve: lanes under load wait this long for more CSTs")
     ap.add_argument("--lanes", type=int, default=2, help="--serve: enumeration lanes (streams)")
-    ap.add_argument("--builders", type=int, default=2, help="--serve: CST builder threads (streams)")
+    ap.add_argument("--builders", type=int, default=4, help="--serve: CST builder threads (streams)")
     ap.add_argument("--skip-plain", action="store_true", help="--serve: only the served form")
     ap.add_argument("--order-rule", type=int, default=1,
                     help="matching order the CSTs are built with first (cstm_tune.order_rule): 1, constraint-first, "
