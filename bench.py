@@ -118,6 +118,11 @@ def roofline_of(kernel_ms, launches, counted, workload):
         "avg_launch_ms": avg_ms,
         "work": {"N": N, "M": M, "F": F, "summed": Nsum, "S": S},
     }
+    chunks = sum(st.get("chunks", 0) for _, st in counted)
+    if chunks and not lds:
+        # visited candidates per lane of the 64-lane rounds that read them
+        out["lane_utilisation"] = (N - Nsum) / (64.0 * chunks)
+        out["work"]["chunks"] = chunks
     if lds:
         on_chip = work / n_launch / sec / 1e9 if sec else 0.0
         out["on_chip"] = {"achieved": on_chip, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": on_chip / LDS_PEAK_GBS,

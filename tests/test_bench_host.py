@@ -68,6 +68,10 @@ def test_roofline_prices_the_enumeration_kernel():
     assert abs(r["achieved"] - alg / 0.020 / 1e9) < 1e-12
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15 and "on_chip" not in r
     assert r["traffic"] is None and r["hbm_gbs"] is None  # no counter summary for this workload
+    assert "lane_utilisation" not in r  # no round counts given
+    counted[0][1]["chunks"], counted[1][1]["chunks"] = 2, 1
+    r = b.roofline_of(40.0, 2, counted, "c3")
+    assert abs(r["lane_utilisation"] - (150 - 40) / (64 * 3)) < 1e-15 and r["work"]["chunks"] == 3
     # LDS images: HBM bytes are the images, the list work is on chip
     counted = [({"bytes": 1000}, _st(1, 0, N=100, M=10, F=5, image_bytes=7000))]
     r = b.roofline_of(50.0, 1, counted, "c3")
