@@ -2,16 +2,19 @@
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c5] [--extras c2,c3]
 
-The main line is the batched form of the billion-edge R-MAT workload (the
-largest configuration that fits one GPU): one step builds the CST of every
-query of the stored set (on several streams at once) and counts them all in
-one persistent launch over a device task queue; each query counts
-min(#embeddings, its stored limit), and every count is checked against the
-value the CPU oracle stored with the workload.  The plain form (one query per
-launch) runs beside it on the same queries, with the enumeration kernel's
-roofline and the oracle timed on the host cores.  Other stored workloads
-(--extras) report their plain and batched forms as extra keys.  Graphs are
-generated from their seeds and made resident before timing starts.
+The main line is the pipelined form of the billion-edge R-MAT workload (the
+largest configuration that fits one GPU): one step submits every query of the
+stored set at once to the library's server, whose builder threads build CSTs
+while its enumeration lanes run persistent launches over the CSTs built so
+far; each query counts min(#embeddings, its stored limit), and every count is
+checked against the value the CPU oracle stored with the workload.  The
+enumeration kernel's roofline comes from the same launches (their kernel time
+measured with HIP events on the lanes' streams).  Beside it, on the same
+queries: the batched single launch (every CST built first, then one launch),
+the plain form (one query per launch), and the oracle timed on the host
+cores.  Other stored workloads (--extras) report their plain and batched
+forms as extra keys.  Graphs are generated from their seeds and made resident
+before timing starts.
 
 Prints one JSON line; exits 1 if a count is wrong.
 
@@ -47,7 +50,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 LDS_PEAK_GBS = 128 * 256 * 2.4
 
 
-PROFILES = {"c5": "c5_rmat26_hbm_counters.md"}
+PROFILES = {"c5": "c5_rmat26_hbm_counters.md", "c5_pipelined": "c5_rmat26_pipelined_hbm_counters.md"}
 
 
 def measured_traffic(workload: str):
@@ -71,7 +74,28 @@ def measured_traffic(workload: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def roofline_of(kernel_ms, launches, counted, workload):
+def measured_step_traffic(key: str):
+    """HBM bytes of one pipelined step (every CST of the workload, over all of
+    the step's launches) from the committed counter summary, or None when there
+    is none or the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2102_10768_amd", "csrc", "enumerate_global.hip")
+    prof = os.path.join(ROOT, "profiles", PROFILES.get(key, "-"))
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(prof):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_prefix") != sha or "traffic_bytes_per_step" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_step"])
+
+
+def roofline_of(kernel_ms, launches, counted, workload, traffic="profile"):
     """Roofline of the enumeration kernel over the timed launches.
 
     ``kernel_ms``: summed duration of the timed launches (HIP events on the
@@ -82,9 +106,10 @@ def roofline_of(kernel_ms, launches, counted, workload):
     candidates counted by list length carry no bytes.  Those bytes come from
     L2/MALL far more than from HBM: the measured HBM traffic per launch, when a
     counter summary for this kernel source exists, is reported beside them
-    (traffic_bytes_per_launch, hbm_gbs).  LDS mode (k_enumerate): the HBM
-    bytes are the staged images; the per-candidate work is priced on chip
-    against the LDS rate."""
+    (traffic_bytes_per_launch, hbm_gbs); ``traffic`` gives those bytes
+    directly (None: not measured) instead of the workload's single-launch
+    summary.  LDS mode (k_enumerate): the HBM bytes are the staged images; the
+    per-candidate work is priced on chip against the LDS rate."""
     N = sum(st["extensions"] for _, st in counted)
     M = sum(st["edge_checks"] for _, st in counted)
     F = sum(st["pushed"] for _, st in counted)
@@ -100,7 +125,8 @@ def roofline_of(kernel_ms, launches, counted, workload):
     avg_ms = kernel_ms / max(1, launches)
     sec = avg_ms * 1e-3
     achieved = alg / sec / 1e9 if sec else 0.0
-    traffic = None if lds else measured_traffic(workload)
+    if traffic == "profile":  # the workload's single-launch counter summary
+        traffic = None if lds else measured_traffic(workload)
     out = {
         "kernel": "k_enumerate" if lds else "k_enumerate_global",
         "bound": "hbm",
@@ -233,10 +259,37 @@ class Session:
             c.close()
         return counts
 
+    def start_server(self, builders: int, lanes: int, wait_us: int, budget: int):
+        """The library's server over the session's graph, for the pipelined form."""
+        from paper_2102_10768_amd import cstm
+
+        self.srv = cstm.Server(self.ctx, self.G, mem_budget=budget, lanes=lanes, builders=builders,
+                               batch_wait_us=wait_us)
+        self.srv_config = {"builders": builders, "lanes": lanes, "batch_wait_us": wait_us, "mem_budget_bytes": budget}
+
+    def pipelined_step(self):
+        """Every query submitted at once to the server: builder threads build
+        CSTs while enumeration lanes launch persistent kernels over whatever
+        has been built.  Returns (counts, server-stat deltas, seconds)."""
+        from paper_2102_10768_amd import serve
+
+        keys = ("launches", "kernel_ms", "extensions", "edge_checks", "pushed", "summed", "chunks")
+        st0 = self.srv.stats()
+        t = time.perf_counter()
+        reqs = serve.replay_native(self.srv, [0.0] * len(self.queries), self.queries,
+                                   limit=self.limits if self.any_limit else 0)
+        dt = time.perf_counter() - t
+        st1 = self.srv.stats()
+        counts = [r.count if r.error is None else -1 for r in reqs]
+        return counts, {k: st1[k] - st0[k] for k in keys}, dt
+
     def bad(self, counts):
         return [i for i, (x, y) in enumerate(zip(counts, self.expected)) if x != y]
 
     def close(self):
+        if getattr(self, "srv", None) is not None:
+            self.srv.close()
+            self.srv = None
         self.G.close()
         self.ctx.close()
 
@@ -265,33 +318,37 @@ def autotune_session(S, a):
 
 
 def headline(a):
-    """The batched form of the main workload: the JSON line's value, roofline
-    and CPU baseline, with the plain form on the same queries beside it."""
+    """The main workload: the pipelined form (the JSON line's value, with its
+    roofline), the batched single launch and the plain form on the same
+    queries, and the CPU baseline."""
+    import torch
+
     S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
     total = sum(S.expected)
     bad = []
     tuned = autotune_session(S, a)
-    # warm-up, with the parity check
+
+    # batched single launch: every CST built (build streams), then one launch
     for _ in range(max(1, a.warmup)):
         counts, _, _, _ = S.batched_step()
         bad += [i for i in S.bad(counts) if i not in bad]
-    say(f"warm-up done; {len(bad)} mismatches")
+    say(f"batched warm-up done; {len(bad)} mismatches")
     steps = []
-    elapsed, outs = timed(lambda: S.batched_step(), a.steps)
+    b_elapsed, outs = timed(lambda: S.batched_step(), a.steps)
     for counts, st, tb, _ in outs:
         bad += [i for i in S.bad(counts) if i not in bad]
         steps.append({"kernel_ms": st["kernel_ms"], "build_s": tb, "launches": st["launches"]})
-    value = total * a.steps / elapsed
-    ms_per_step = 1e3 * elapsed / a.steps
-    say(f"batched: {ms_per_step:.1f} ms/step, {value:.3e} embeddings/s")
-    kernel_ms = sum(x["kernel_ms"] for x in steps)
-    launches = sum(x["launches"] for x in steps)
+    b_value = total * a.steps / b_elapsed
+    say(f"batched: {1e3 * b_elapsed / a.steps:.1f} ms/step, {b_value:.3e} embeddings/s")
+    b_kernel_ms = sum(x["kernel_ms"] for x in steps)
+    b_launches = sum(x["launches"] for x in steps)
     # one counter pass over the same launch (work done, for the roofline)
     S.ctx.tune = {"collect_stats": 1}
     counts, st, _, infos = S.batched_step()
     S.ctx.tune = {"collect_stats": 0}
     bad += [i for i in S.bad(counts) if i not in bad]
-    roof = roofline_of(kernel_ms, launches, [(dict(bytes=sum(i["bytes"] for i in infos)), st)], a.workload)
+    cst_bytes = sum(i["bytes"] for i in infos)
+    b_roof = roofline_of(b_kernel_ms, b_launches, [(dict(bytes=cst_bytes), st)], a.workload)
     # the same batched launch visiting every last-level candidate (no list-length sums)
     S.ctx.tune = {"last_level_sum": -1}
     tv = time.perf_counter()
@@ -299,14 +356,51 @@ def headline(a):
     visit_s = time.perf_counter() - tv
     S.ctx.tune = {"last_level_sum": 1}
     bad += [i for i in S.bad(vcounts) if i not in bad]
+
+    # pipelined (main line): all queries submitted at once to the server;
+    # builds overlap the persistent launches of what has been built
+    S.start_server(a.pipe_builders, a.pipe_lanes, a.pipe_wait_us, int(a.pipe_budget_gb * (1 << 30)))
+    for _ in range(max(1, a.warmup)):
+        counts, _, _ = S.pipelined_step()
+        bad += [i for i in S.bad(counts) if i not in bad]
+    say(f"pipelined warm-up done; {len(bad)} mismatches")
+    torch.cuda.synchronize()
+    window = [time.monotonic_ns()]  # CLOCK_MONOTONIC, the clock of rocprofv3's timestamps
+    t = time.perf_counter()
+    pouts = [S.pipelined_step() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    window.append(time.monotonic_ns())
+    for counts, _, _ in pouts:
+        bad += [i for i in S.bad(counts) if i not in bad]
+    value = total * a.steps / elapsed
+    ms_per_step = 1e3 * elapsed / a.steps
+    p_kernel_ms = sum(d["kernel_ms"] for _, d, _ in pouts)
+    p_launches = sum(d["launches"] for _, d, _ in pouts)
+    say(f"pipelined: {ms_per_step:.1f} ms/step, {value:.3e} embeddings/s, {p_launches / a.steps:.1f} launches/step")
+    S.ctx.tune = {"collect_stats": 1}
+    counts, d, _ = S.pipelined_step()
+    S.ctx.tune = {"collect_stats": 0}
+    bad += [i for i in S.bad(counts) if i not in bad]
+    p_stats = {"mode": 2, "extensions": d["extensions"], "edge_checks": d["edge_checks"], "pushed": d["pushed"],
+               "summed": d["summed"], "chunks": d["chunks"], "launches": d["launches"], "image_bytes": 0}
+    step_traffic = measured_step_traffic(a.workload + "_pipelined")
+    roof = roofline_of(p_kernel_ms, p_launches, [(dict(bytes=cst_bytes), p_stats)], a.workload,
+                       traffic=step_traffic * a.steps / p_launches if (step_traffic and p_launches) else None)
+    roof["traffic_bytes_per_step"] = step_traffic
+    roof["timed_window_monotonic_ns"] = window
+    roof["algorithmic_gbs_over_the_step"] = ((cst_bytes + 4 * (p_stats["extensions"] - p_stats["summed"])
+                                              + 4 * p_stats["edge_checks"] + 8 * p_stats["pushed"])
+                                             / (ms_per_step * 1e-3) / 1e9)
+
     # plain form on the same queries, one step
     per_query = []
-    p_elapsed, pouts = timed(lambda: S.plain_step(per_query), 1)
-    bad += [i for i in S.bad(pouts[0]) if i not in bad]
-    plain_value = total / p_elapsed
+    pl_elapsed, plouts = timed(lambda: S.plain_step(per_query), 1)
+    bad += [i for i in S.bad(plouts[0]) if i not in bad]
+    plain_value = total / pl_elapsed
     build_ms = sum(r[2]["build_ms"] for r in per_query)
     enum_ms = sum(r[2]["enumerate_ms"] for r in per_query)
-    say(f"plain: {1e3 * p_elapsed:.1f} ms/step, {plain_value:.3e} embeddings/s")
+    say(f"plain: {1e3 * pl_elapsed:.1f} ms/step, {plain_value:.3e} embeddings/s")
     gs = S.W["graph_summary"]
     out = {
         "metric": "embeddings/sec",
@@ -328,26 +422,39 @@ def headline(a):
             "queries_inf_at_oracle_screen": S.inf,
             "result_limit_per_query": max(S.limits) if S.any_limit else 0,
             "embeddings_per_step": total,
-            "form": f"batched: every CST built ({len(S.streams)} build streams), then one persistent launch "
-                    "over a device task queue",
+            "form": f"pipelined: every query of the step submitted at once to the library's server "
+                    f"({a.pipe_builders} CST builder threads, {a.pipe_lanes} enumeration lanes); builds overlap "
+                    "persistent launches over the CSTs built so far",
+            "server": S.srv_config,
             "enum_mode": a.mode,
             "order_rule": S.ctx.tune["order_rule"],
             "graph": {k: gs[k] for k in ("n", "m", "max_degree") if k in gs},
         },
-        "parity": {"checked": len(S.expected), "mismatches": len(bad), "runs_checked": a.warmup + a.steps + 3},
+        "parity": {"checked": len(S.expected), "mismatches": len(bad), "runs_checked": 2 * (a.warmup + a.steps) + 4},
         "stages_ms_per_step": {
-            "cst_builds_wall": 1e3 * sum(x["build_s"] for x in steps) / len(steps),
-            "enumeration_kernel": kernel_ms / len(steps),
+            "enumeration_kernel_summed_over_lanes": p_kernel_ms / a.steps,
+            "launches": p_launches / a.steps,
+        },
+        "batched": {
+            "value": b_value,
+            "ms_per_step": 1e3 * b_elapsed / a.steps,
+            "form": f"every CST built ({len(S.streams)} build streams), then one persistent launch over a device "
+                    "task queue",
+            "stages_ms_per_step": {
+                "cst_builds_wall": 1e3 * sum(x["build_s"] for x in steps) / len(steps),
+                "enumeration_kernel": b_kernel_ms / len(steps),
+            },
+            "roofline": b_roof,
         },
         "plain": {
             "value": plain_value,
-            "ms_per_step": 1e3 * p_elapsed,
+            "ms_per_step": 1e3 * pl_elapsed,
             "form": "one query per launch: build its CST, count it",
             "stages_ms_per_step": {"cst_build": build_ms, "enumerate": enum_ms},
-            "batched_vs_plain": value / plain_value if plain_value else None,
+            "pipelined_vs_plain": value / plain_value if plain_value else None,
         },
         "last_level_sum": {
-            "summed_fraction_of_N": roof["work"]["summed"] / roof["work"]["N"] if roof["work"]["N"] else 0.0,
+            "summed_fraction_of_N": b_roof["work"]["summed"] / b_roof["work"]["N"] if b_roof["work"]["N"] else 0.0,
             "value_visiting_every_candidate": total / visit_s,
             "visiting_kernel_ms": vst["kernel_ms"],
         },
@@ -446,6 +553,18 @@ def profile_launch(a):
     S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
     if a.tune:
         S.ctx.tune = json.loads(a.tune)
+    if a.pipelined:
+        S.start_server(a.pipe_builders, a.pipe_lanes, a.pipe_wait_us, int(a.pipe_budget_gb * (1 << 30)))
+        counts, d, dt = S.pipelined_step()
+        bad = S.bad(counts)
+        print(json.dumps({"workload": a.workload, "form": "pipelined", "queries": len(S.queries),
+                          "embeddings": sum(counts), "mismatches": len(bad), "step_s": dt,
+                          "launches": d["launches"], "kernel_ms_summed": d["kernel_ms"], "tune": S.ctx.tune}),
+              flush=True)
+        S.close()
+        if bad:
+            sys.exit(1)
+        return
     counts, st, tb, _ = S.batched_step()
     bad = S.bad(counts)
     print(json.dumps({"workload": a.workload, "queries": len(S.queries), "embeddings": sum(counts),
@@ -510,6 +629,10 @@ def main():
     ap.add_argument("--extras", default="c2,c3", help="other stored workloads reported beside the main one")
     ap.add_argument("--mode", default="auto", choices=["auto", "hbm", "lds"])
     ap.add_argument("--build-streams", type=int, default=8, help="streams (host threads) building CSTs in parallel")
+    ap.add_argument("--pipe-builders", type=int, default=8, help="pipelined form: the server's CST builder threads")
+    ap.add_argument("--pipe-lanes", type=int, default=4, help="pipelined form: the server's enumeration lanes")
+    ap.add_argument("--pipe-wait-us", type=int, default=2000, help="pipelined form: a busy lane's batching window")
+    ap.add_argument("--pipe-budget-gb", type=float, default=200.0, help="pipelined form: the server's memory budget")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)
@@ -537,6 +660,7 @@ def main():
     ap.add_argument("--profile-launch", action="store_true",
                     help="only one batched step of --workload (for rocprofv3 runs; one JSON line)")
     ap.add_argument("--tune", default="", help="tuning (JSON dict of cstm_tune fields) for --profile-launch")
+    ap.add_argument("--pipelined", action="store_true", help="--profile-launch: one pipelined step instead")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described "

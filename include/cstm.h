@@ -425,6 +425,12 @@ typedef struct {
     int32_t reserved;
     uint64_t admission_bytes; /* what admission may charge: mem_budget less the lanes'
                                  task rings                                          */
+    /* Summed over the enumeration launches that succeeded: kernel time (HIP
+     * events on each lane's stream) and, when the context collects
+     * statistics (cstm_tune.collect_stats), the work counters of
+     * cstm_enum_stats.                                                          */
+    double kernel_ms;
+    uint64_t extensions, edge_checks, pushed, summed, chunks;
 } cstm_server_stats;
 
 cstm_status cstm_server_create(cstm_ctx* ctx, const cstm_graph* g, uint64_t mem_budget, int32_t lanes,

@@ -405,7 +405,8 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
 // Enumerate nq CSTs: pick LDS images or the HBM-resident CST per the tuning,
 // run at most one launch of each kind, and return per-CST counts.
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
-                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s) {
+                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s,
+                        cstm_enum_stats* st_out) {
     const cstm_tune T = ctx->tune;
     std::vector<cstm_cst*> lds_q, hbm_q;
     std::vector<int> lds_slot, hbm_slot;
@@ -436,7 +437,7 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
     DevArena mem;
     mem.ctx = ctx;
     unsigned long long* counts = mem.get_n<unsigned long long>(nq + 1);
-    HIP_TRY(hipMemsetAsync(counts, 0, (nq + 1) * sizeof(unsigned long long), s));
+    cstm_fill_words(counts, (nq + 1) * sizeof(unsigned long long), 0u, s);  // a kernel, not a memset node
     unsigned long long* row_cursor = counts + nq;
     cstm_enum_stats st{};
     if (!lds_q.empty())
@@ -452,6 +453,7 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
         std::lock_guard<std::mutex> lk(ctx->ws_mu);
         ctx->last_enum = st;
     }
+    if (st_out) *st_out = st;
     for (int q = 0; q < nq; ++q) {
         counts_host[q] = h[q];
         // a launch passes a limit before it stops, and LDS mode counts everything

@@ -358,5 +358,8 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
 void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const int* slot, int list, int32_t* rows,
                                uint64_t cap, unsigned long long* counts_dev, unsigned long long* row_cursor,
                                const EnumOpts& o, cstm_enum_stats* st, hipStream_t s);
+// *st_out (may be NULL) receives the launch statistics (also kept as the
+// context's last ones).
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
-                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s);
+                        uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s,
+                        cstm_enum_stats* st_out = nullptr);

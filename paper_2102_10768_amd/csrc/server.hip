@@ -195,16 +195,25 @@ struct cstm_server {
                 r->res.launch_s = t_launch;
             }
             counts.assign(batch.size(), 0);
+            cstm_enum_stats es{};
             cstm_status e = cstm_guard([&] {
                 EnumOpts o;
                 o.limits = any_limit ? limits.data() : nullptr;
                 o.deadline_ms = ctx->tune.deadline_ms;
                 o.force_hbm = true;  // admission charged the CSTs, not partition images
-                cstm_enumerate_run(ctx, (int)csts.size(), csts.data(), 0, nullptr, 0, counts.data(), nullptr, o, s);
+                cstm_enumerate_run(ctx, (int)csts.size(), csts.data(), 0, nullptr, 0, counts.data(), nullptr, o, s, &es);
             });
             {
                 std::lock_guard<std::mutex> lk(mu);
                 busy_lanes--;
+                if (e == CSTM_OK) {
+                    st.kernel_ms += es.kernel_ms;
+                    st.extensions += es.extensions;
+                    st.edge_checks += es.edge_checks;
+                    st.pushed += es.pushed;
+                    st.summed += es.summed;
+                    st.chunks += es.chunks;
+                }
             }
             for (size_t i = 0; i < batch.size(); ++i) finish(batch[i], e, counts[i]);
         }

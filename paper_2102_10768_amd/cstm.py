@@ -114,6 +114,12 @@ class cstm_server_stats(ctypes.Structure):
         ("max_overlap", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("admission_bytes", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
+        ("extensions", ctypes.c_uint64),
+        ("edge_checks", ctypes.c_uint64),
+        ("pushed", ctypes.c_uint64),
+        ("summed", ctypes.c_uint64),
+        ("chunks", ctypes.c_uint64),
     ]
 
 
