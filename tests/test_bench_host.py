@@ -108,3 +108,27 @@ def test_cpu_baseline_samples_stored_queries_and_checks_finished_counts():
     assert one["cores"] == 1 and allc["cores"] >= 1
     for r in (allc, one):
         assert r["value"] > 0 and r["kind"] == "oracle" and "4 finished" in r["sample"]
+
+
+def test_pipelined_step_traffic_is_read_for_the_profiled_kernel_source(tmp_path):
+    b = _bench()
+    for d in ("profiles", os.path.join("paper_2102_10768_amd", "csrc")):
+        os.makedirs(tmp_path / d)
+    src = os.path.join("paper_2102_10768_amd", "csrc", "enumerate_global.hip")
+    prof = os.path.join("profiles", "c5_rmat26_pipelined_hbm_counters.md")
+    shutil.copy(os.path.join(ROOT, src), tmp_path / src)
+    shutil.copy(os.path.join(ROOT, prof), tmp_path / prof)
+    b.ROOT = str(tmp_path)
+    want = None
+    for line in open(tmp_path / prof):
+        if line.startswith("traffic_bytes_per_step:"):
+            want = float(line.split(":")[1])
+    assert b.measured_step_traffic("c5_pipelined") in (want, None)
+    assert b.measured_step_traffic("c5") is None  # the single-launch summary has no per-step figure
+    with open(tmp_path / src, "a") as f:
+        f.write("\n// changed\n")
+    assert b.measured_step_traffic("c5_pipelined") is None
+    # an explicit traffic figure replaces the profile; None means not measured
+    counted = [({"bytes": 1000}, _st(2, 0, N=100, M=10, F=5, summed=40))]
+    assert b.roofline_of(10.0, 1, counted, "c5", traffic=None)["traffic"] is None
+    assert b.roofline_of(10.0, 1, counted, "c5", traffic=123.0)["traffic_bytes_per_launch"] == 123.0

@@ -149,3 +149,35 @@ def test_native_server_on_the_16m_vertex_graph():
     assert st["peak_bytes"] <= st["admission_bytes"]
     G.close()
     c.close()
+
+
+def test_server_sums_kernel_time_and_work_over_its_launches():
+    """cstm_server_stats: kernel time over the launches, and with statistics
+    on, the work counters, equal the sums of the same launches' statistics;
+    counts equal the stored ones."""
+    from paper_2102_10768_amd import cstm, serve
+
+    W = _load("c1")
+    g = make_graph(W["workload"]["graph"])
+    c = cstm.Context(0, tune={"enum_mode": cstm.MODE_HBM, "collect_stats": 1})
+    G = gpu_graph_in(c, g)
+    pool = [Query.from_dict(d) for d in W["queries"]]
+    expected = [int(d["count"]) for d in W["queries"]]
+    with cstm.Server(c, G, mem_budget=8 << 30, lanes=1, builders=2, batch_wait_us=0) as srv:
+        reqs = serve.replay_native(srv, [0.0] * len(pool), pool)
+        st = srv.stats()
+    assert [r.count for r in reqs] == expected
+    assert st["launches"] >= 1 and st["kernel_ms"] > 0
+    # every embedding is one extension at the last level (read or summed)
+    assert st["extensions"] >= sum(expected) and st["summed"] <= st["extensions"] and st["chunks"] > 0
+    # the same CSTs counted one per launch do about the same work (candidates
+    # re-checked after a donation vary with timing)
+    ext = 0
+    for q in pool:
+        cs = cstm.CST(c, G, q.qlabel, q.qedges)
+        cs.count()
+        ext += c.last_enum_stats()["extensions"]
+        cs.close()
+    assert ext / 2 <= st["extensions"] <= 2 * ext
+    G.close()
+    c.close()
