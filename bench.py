@@ -425,7 +425,8 @@ def headline(a):
             "form": f"pipelined: every query of the step submitted at once to the library's server "
                     f"({a.pipe_builders} CST builder threads, {a.pipe_lanes} enumeration lanes); builds overlap "
                     "persistent launches over the CSTs built so far",
-            "server": S.srv_config,
+            "server": {**S.srv_config, "serve_wgs_per_cu": S.ctx.tune["serve_wgs_per_cu"],
+                       "hbm_wgs_per_cu": S.ctx.tune["hbm_wgs_per_cu"]},
             "enum_mode": a.mode,
             "order_rule": S.ctx.tune["order_rule"],
             "graph": {k: gs[k] for k in ("n", "m", "max_degree") if k in gs},

@@ -124,7 +124,12 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      parent is placed with the most placed query neighbours
  *                      (then the larger query degree, then the smaller id),
  *                      so that non-tree edges are checked early.  Any such
- *                      order gives the same embeddings (Section VII-C).     */
+ *                      order gives the same embeddings (Section VII-C).
+ *   serve_wgs_per_cu   cstm_server lanes: 256-thread workgroups per compute
+ *                      unit of a launch made while CST builds are still
+ *                      queued or running (default 2, which leaves room on
+ *                      each CU for the build kernels); a launch with no build
+ *                      in flight uses hbm_wgs_per_cu.                       */
 #define CSTM_MODE_AUTO 0
 #define CSTM_MODE_LDS 1
 #define CSTM_MODE_HBM 2
@@ -146,6 +151,7 @@ typedef struct {
     int32_t batch_order;
     int32_t hbm_idle_ms;
     int32_t order_rule;
+    int32_t serve_wgs_per_cu;
 } cstm_tune;
 
 /* What the last enumeration launch on a context did (Section VI-B's counts).

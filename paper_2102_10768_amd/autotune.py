@@ -13,7 +13,8 @@ fast that launch runs depends on knobs that leave every count unchanged:
   size the last level is expanded flat (``hbm_flat_max``).
 
 :func:`tune` times candidate settings on a seeded calibration subset of the
-batch (by default 5 %, seed 301) by coordinate descent: first the mode, then
+batch (by default 20 %, seed 301; a smaller subset cannot fill the GPU, so it
+favours narrower grids) by coordinate descent: first the mode, then
 each knob of that mode over a short list of values, keeping the best so far.
 Every candidate's counts must equal those of the first setting tried; a
 candidate that changes a count is rejected and reported.  After the first,
@@ -49,7 +50,7 @@ MODE_START = {
 }
 
 
-def calibration_subset(n: int, frac: float = 0.05, seed: int = 301, min_n: int = 8) -> list[int]:
+def calibration_subset(n: int, frac: float = 0.2, seed: int = 301, min_n: int = 8) -> list[int]:
     """Sorted indices of a seeded random subset of ``max(min_n, frac * n)`` of ``n`` items."""
     m = min(n, max(min_n, int(round(frac * n))))
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -76,7 +77,7 @@ def _time_setting(ctx, graph, queries, setting: dict, repeats: int, stream, limi
     return best, counts
 
 
-def tune(ctx, graph, queries, *, frac: float = 0.05, seed: int = 301, repeats: int = 2,
+def tune(ctx, graph, queries, *, frac: float = 0.2, seed: int = 301, repeats: int = 2,
          modes=("hbm", "lds"), stream=None, log=None, limits=None) -> dict:
     """Choose launch parameters for ``batch_count`` over ``queries`` (see the module docstring).
 

@@ -154,6 +154,7 @@ static void apply_defaults(cstm_ctx* c) {
     if (t.hbm_donate_min <= 0) t.hbm_donate_min = 16;
     if (t.hbm_idle_ms <= 0) t.hbm_idle_ms = 30000;
     if (t.order_rule < 0 || t.order_rule > 1) t.order_rule = 0;
+    if (t.serve_wgs_per_cu <= 0) t.serve_wgs_per_cu = 2;
 }
 
 extern "C" cstm_status cstm_ctx_create(int device, cstm_alloc_fn alloc, cstm_free_fn free_fn, void* user,

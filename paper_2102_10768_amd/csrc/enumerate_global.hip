@@ -1013,7 +1013,7 @@ void cstm_enumerate_global_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, con
     k_seed<<<cstm_blocks((int64_t)total, 256, 4096), 256, 0, s>>>(A, meta, meta + ns + 1, meta + 2 * ns + 1,
                                                                   meta + 3 * ns + 1, dsegq, ns, total);
     HIP_TRY(hipGetLastError());
-    const unsigned grid = (unsigned)(ctx->num_cus * ctx->tune.hbm_wgs_per_cu);
+    const unsigned grid = (unsigned)(ctx->num_cus * (o.wgs_per_cu > 0 ? o.wgs_per_cu : ctx->tune.hbm_wgs_per_cu));
     float kernel_ms = 0;
     if (fixed) {
         k_enumerate_global<<<grid, 256, 0, s>>>(A);

@@ -346,6 +346,8 @@ struct EnumOpts {
     size_t fixed_ws_bytes = 0;
     // every CST of the call in device memory (no partitioning at launch), whatever tune.enum_mode says
     bool force_hbm = false;
+    // HBM-resident kernel: workgroups per CU of the launch (0: tune.hbm_wgs_per_cu)
+    int wgs_per_cu = 0;
 };
 // Device bytes the context lends one HBM-mode launch of nq CSTs.
 size_t cstm_hbm_workspace_bytes(int nq);

@@ -156,6 +156,7 @@ struct cstm_server {
         std::vector<Request*> batch;
         std::vector<cstm_cst*> csts;
         std::vector<uint64_t> counts, limits;
+        bool builds_in_flight = false;
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -177,6 +178,8 @@ struct cstm_server {
                     batch.push_back(ready.front());
                     ready.pop_front();
                 }
+                // builds still to come share the CUs with this launch
+                builds_in_flight = !pending.empty() || unbuilt > 0;
                 busy_lanes++;
                 if (busy_lanes > st.max_overlap) st.max_overlap = busy_lanes;
                 st.launches++;
@@ -201,6 +204,7 @@ struct cstm_server {
                 o.limits = any_limit ? limits.data() : nullptr;
                 o.deadline_ms = ctx->tune.deadline_ms;
                 o.force_hbm = true;  // admission charged the CSTs, not partition images
+                if (builds_in_flight) o.wgs_per_cu = ctx->tune.serve_wgs_per_cu;
                 cstm_enumerate_run(ctx, (int)csts.size(), csts.data(), 0, nullptr, 0, counts.data(), nullptr, o, s, &es);
             });
             {

@@ -47,6 +47,7 @@ class cstm_tune(ctypes.Structure):
         ("batch_order", ctypes.c_int32),
         ("hbm_idle_ms", ctypes.c_int32),
         ("order_rule", ctypes.c_int32),
+        ("serve_wgs_per_cu", ctypes.c_int32),
     ]
 
 
