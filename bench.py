@@ -274,13 +274,17 @@ class Session:
         from paper_2102_10768_amd import serve
 
         keys = ("launches", "kernel_ms", "extensions", "edge_checks", "pushed", "summed", "chunks")
+        # larger queries first, so that no long search starts last
+        order = sorted(range(len(self.queries)), key=lambda i: -self.queries[i].k)
         st0 = self.srv.stats()
         t = time.perf_counter()
-        reqs = serve.replay_native(self.srv, [0.0] * len(self.queries), self.queries,
-                                   limit=self.limits if self.any_limit else 0)
+        reqs = serve.replay_native(self.srv, [0.0] * len(order), [self.queries[i] for i in order],
+                                   limit=[self.limits[i] for i in order] if self.any_limit else 0)
         dt = time.perf_counter() - t
         st1 = self.srv.stats()
-        counts = [r.count if r.error is None else -1 for r in reqs]
+        counts = [0] * len(order)
+        for i, r in zip(order, reqs):
+            counts[i] = r.count if r.error is None else -1
         return counts, {k: st1[k] - st0[k] for k in keys}, dt
 
     def bad(self, counts):
@@ -422,9 +426,9 @@ def headline(a):
             "queries_inf_at_oracle_screen": S.inf,
             "result_limit_per_query": max(S.limits) if S.any_limit else 0,
             "embeddings_per_step": total,
-            "form": f"pipelined: every query of the step submitted at once to the library's server "
-                    f"({a.pipe_builders} CST builder threads, {a.pipe_lanes} enumeration lanes); builds overlap "
-                    "persistent launches over the CSTs built so far",
+            "form": f"pipelined: every query of the step submitted at once (larger queries first) to the "
+                    f"library's server ({a.pipe_builders} CST builder threads, {a.pipe_lanes} enumeration lanes); "
+                    "builds overlap persistent launches over the CSTs built so far",
             "server": {**S.srv_config, "serve_wgs_per_cu": S.ctx.tune["serve_wgs_per_cu"],
                        "hbm_wgs_per_cu": S.ctx.tune["hbm_wgs_per_cu"]},
             "enum_mode": a.mode,
