@@ -681,15 +681,22 @@ def main():
         from synth import make_graph
 
         W = load_workload(a.workload)
-        queries, expected, _, _ = workload_queries(W, a.max_queries)
+        queries, expected, limits, _ = workload_queries(W, a.max_queries)
+        if a.share:
+            # the host share counts every embedding: only queries stored with
+            # their exact total (no result limit) take part
+            keep = [i for i, lim in enumerate(limits) if not lim]
+            say(f"share sweep over the {len(keep)} of {len(queries)} queries stored without a result limit")
+            queries, expected, limits = ([queries[i] for i in keep], [expected[i] for i in keep],
+                                         [limits[i] for i in keep])
         t0 = time.time()
         g = make_graph(W["workload"]["graph"], log=say)
         say(f"graph ready in {time.time() - t0:.1f}s: {g.summary()}")
         if a.serve:
-            return serve_main(a, W, g, queries, expected)
+            return serve_main(a, W, g, queries, expected, limits)
         if a.share:
             return share_main(a, W, g, queries, expected)
-        return orders_main(a, W, g, queries, expected)
+        return orders_main(a, W, g, queries, expected, limits)
 
     out, bad = headline(a)
     out["hbm_copy_ceiling"] = copy_ceiling()
@@ -778,7 +785,7 @@ def share_main(a, W, g, queries, expected):
     ctx.close()
 
 
-def orders_main(a, W, g, queries, expected):
+def orders_main(a, W, g, queries, expected, limits):
     """Matching-order study (Section VII-C): per query, the enumeration kernel
     time under the path-based order and under a.orders random orders that
     start at the CST root and follow the BFS tree (seeded); counts checked, a
@@ -794,11 +801,11 @@ def orders_main(a, W, g, queries, expected):
     rng = np.random.default_rng(5)
     deadline_s = 2.0
     per = []
-    for i, (q, want) in enumerate(zip(queries, expected)):
+    for i, (q, want, lim) in enumerate(zip(queries, expected, limits)):
         c = cstm.CST(ctx, G, q.qlabel, q.qedges)
         info = c.info()
-        c.count()
-        if c.count() != want:
+        c.count(limit=lim)
+        if c.count(limit=lim) != want:
             raise SystemExit(f"count mismatch on query {i}")
         t_def = ctx.last_enum_stats()["kernel_ms"]
         c.close()
@@ -812,8 +819,8 @@ def orders_main(a, W, g, queries, expected):
                 placed.add(u)
             c = cstm.CST(ctx, G, q.qlabel, q.qedges, order=order)
             try:
-                c.count(deadline_s=deadline_s)
-                if c.count(deadline_s=deadline_s) != want:
+                c.count(deadline_s=deadline_s, limit=lim)
+                if c.count(deadline_s=deadline_s, limit=lim) != want:
                     raise SystemExit(f"count mismatch on query {i} under order {order}")
                 times.append(ctx.last_enum_stats()["kernel_ms"])
             except cstm.CstmError as e:
@@ -840,7 +847,7 @@ def orders_main(a, W, g, queries, expected):
     ctx.close()
 
 
-def serve_main(a, W, g, queries, expected):
+def serve_main(a, W, g, queries, expected, limits):
     """Served form vs the plain one-at-a-time form on the same Poisson request streams."""
     import numpy as np
     import torch
@@ -858,12 +865,11 @@ def serve_main(a, W, g, queries, expected):
     if len(seeds) < len(rates):
         seeds = [201 + i for i in range(len(rates))]
     budget = int((a.mem_budget_gb or spec.get("mem_budget_gb", 64)) * (1 << 30))
-    # each request asks for min(total, limit) when the workload sets a result limit
-    limit = int(W["workload"]["queries"].get("limit", 0))
+    # each request asks for min(total, its query's stored limit)
     # warm-up: every query once, alone (also the check that the pool's counts hold)
-    for q, e in zip(queries, expected):
+    for q, e, lim in zip(queries, expected, limits):
         c = cstm.CST(ctx, G, q.qlabel, q.qedges)
-        n = c.count(limit=limit)
+        n = c.count(limit=lim)
         c.close()
         if n != e:
             print(f"COUNT MISMATCH in warm-up: {n} != {e}", file=sys.stderr)
@@ -877,6 +883,7 @@ def serve_main(a, W, g, queries, expected):
         picks = np.random.Generator(np.random.PCG64(301 + i)).integers(0, len(queries), size=n)
         qs = [queries[int(p)] for p in picks]
         want = [expected[int(p)] for p in picks]
+        limit = [limits[int(p)] for p in picks]
         with cstm.Server(ctx, G, mem_budget=budget, lanes=a.lanes, builders=a.builders,
                          batch_wait_us=a.batch_wait_us) as srv:
             served = serve.replay_native(srv, arr, qs, limit=limit)
@@ -917,7 +924,7 @@ def serve_main(a, W, g, queries, expected):
             "batch_wait_us": a.batch_wait_us,
             "order_rule": a.order_rule,
             "query_pool": len(queries),
-            "result_limit": limit,
+            "result_limits": sorted(set(int(x) for x in limits)),
             "mem_budget_bytes": budget,
         },
         "parity": {"checked": 2 * sum(r["requests"] for r in rows), "mismatches": mismatches},
