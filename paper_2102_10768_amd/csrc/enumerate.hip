@@ -336,7 +336,7 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     DevArena mem;
     mem.ctx = ctx;
     unsigned long long* work = mem.get_n<unsigned long long>(8);
-    HIP_TRY(hipMemsetAsync(work, 0, 8 * sizeof(unsigned long long), s));
+    cstm_fill_words(work, 8 * sizeof(unsigned long long), 0u, s);  // a kernel, not a memset node
     uint64_t* bl = mem.get_n<uint64_t>(total);
     int32_t* qi = mem.get_n<int32_t>(total);
     std::vector<int32_t> hq(total);
