@@ -452,3 +452,40 @@ def test_label_edge_table_matches_the_csr():
         np.add.at(want, (g.label[src], g.label[g.col]), 1)
         assert t.shape == (L, L) and np.array_equal(t, want)
         assert int(t.sum()) == int(g.row_ptr[-1])
+
+
+def test_sparse_label_space_takes_the_64_bit_keys():
+    """Labels up to 2^20 with a label group of 2,600 vertices need 21 + 12 = 33
+    key bits, so G keeps 64-bit packed keys and 64-bit label-grouped rows (and
+    no label-pair table): counts and sorted lists still equal the oracle's."""
+    from synth.graphs import Graph, erdos_renyi
+
+    rng = np.random.default_rng(61)
+    n = 3000
+    row_ptr, col = erdos_renyi(n, 10 / (n - 1), 61)
+    lab = np.zeros(n, dtype=np.int32)
+    lab[rng.choice(n, 300, replace=False)] = 1
+    lab[rng.choice(n, 100, replace=False)] = 1 << 20
+    g = Graph(n, row_ptr, col, lab, "sparse-labels")
+    G = gpu_graph(g)
+    assert G.label_edges() is None  # more than 128 labels
+    from synth import Query
+
+    big = 1 << 20  # queries that use the largest label too
+    small = query_set(g, [2, 3, 3], 62) + [
+        Query(np.array([big, 0], dtype=np.int32), np.array([[0, 1]], dtype=np.int32)),
+        Query(np.array([0, big, 1], dtype=np.int32), np.array([[0, 1], [1, 2]], dtype=np.int32)),
+    ]  # listed: at most a few 10^5 rows
+    large = query_set(g, [4, 5], 63)     # counted
+    for mode in MODES:
+        Gm = gpu_graph(g, mode)
+        for q in small:
+            say(f"sparse labels ({mode}): k={q.k} labels={sorted(set(q.qlabel))} (lists)")
+            want_n, want_rows = _oracle_rows(g, q)
+            n_got, rows = gpu_rows(Gm, q)
+            assert n_got == want_n and rows == want_rows
+        for q in large:
+            say(f"sparse labels ({mode}): k={q.k} labels={sorted(set(q.qlabel))} (counts)")
+            want = oracle.match(g, q)
+            assert want.status == oracle.OK
+            assert gpu_count(Gm, q, partition=mode == "lds")[0] == want.count
