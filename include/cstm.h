@@ -224,9 +224,9 @@ cstm_status cstm_ctx_lds_bytes(const cstm_ctx* ctx, int64_t* out);
  * time (24 bytes of temporary device memory per entry); a chunk grows past
  * that only by its last row, and one of 2^31 entries or more (a row of more
  * than about 1.88 * 10^9 entries) gives CSTM_EINVAL.  n must be < 2^31 and
- * labels below 2^26; the label tables take about 280 host bytes and 16
- * device bytes per label value up to the largest one, so sparse label values
- * are best renumbered densely first. */
+ * labels below 2^26; the label tables take about 280 bytes per label value
+ * up to the largest one, on the host and (while loading) on the device, so
+ * sparse label values are best renumbered densely first. */
 cstm_status cstm_graph_load(cstm_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                             const int32_t* col, const int32_t* label, int on_device, void* stream,
                             cstm_graph** out);
