@@ -162,19 +162,27 @@ def load_workload(name: str):
         return json.load(f)
 
 
-def workload_queries(W, max_queries: int = 0):
+def workload_queries(W, max_queries: int = 0, exact_only: bool = False):
     """(queries, expected counts, per-query limits, INF count) of a stored set;
-    queries the oracle left INF (no stored count) are not run."""
+    queries the oracle left INF (no stored count) are not run.  With
+    ``exact_only`` only the queries whose stored count is the exact total
+    (stored without a limit, or below it) are kept, and they run unlimited."""
     from synth import Query
 
     rows = [d for d in W["queries"] if d.get("count") is not None]
     inf = len(W["queries"]) - len(rows)
+    lim_all = int(W["workload"]["queries"].get("limit", 0))
+
+    def limit_of(d):
+        return int(d.get("limit", lim_all) or 0)
+
+    if exact_only:
+        rows = [d for d in rows if not limit_of(d) or int(d["count"]) < limit_of(d)]
     if max_queries:
         rows = rows[:max_queries]
-    lim_all = int(W["workload"]["queries"].get("limit", 0))
     queries = [Query.from_dict(d) for d in rows]
     expected = [int(d["count"]) for d in rows]
-    limits = [int(d.get("limit", lim_all) or 0) for d in rows]
+    limits = [0 if exact_only else limit_of(d) for d in rows]
     return queries, expected, limits, inf
 
 
@@ -186,7 +194,7 @@ class Session:
     """One workload resident on the device, with the forms the benchmark times."""
 
     def __init__(self, name: str, mode: str = "auto", build_streams: int = 4, max_queries: int = 0,
-                 order_rule: int = 1):
+                 order_rule: int = 1, exact_only: bool = False):
         import torch
 
         from paper_2102_10768_amd import cstm
@@ -194,7 +202,8 @@ class Session:
 
         self.name = name
         self.W = load_workload(name)
-        self.queries, self.expected, self.limits, self.inf = workload_queries(self.W, max_queries)
+        self.queries, self.expected, self.limits, self.inf = workload_queries(self.W, max_queries, exact_only)
+        self.exact_only = exact_only
         say(f"workload {name}: {len(self.queries)} queries ({self.inf} INF at the oracle screen); generating graph")
         t0 = time.time()
         self.g = make_graph(self.W["workload"]["graph"], log=say)
@@ -327,7 +336,7 @@ def headline(a):
     queries, and the CPU baseline."""
     import torch
 
-    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule, a.exact_only)
     total = sum(S.expected)
     bad = []
     tuned = autotune_session(S, a)
@@ -425,6 +434,7 @@ def headline(a):
             "queries": len(S.queries),
             "queries_inf_at_oracle_screen": S.inf,
             "result_limit_per_query": max(S.limits) if S.any_limit else 0,
+            "exact_totals_only": S.exact_only,
             "embeddings_per_step": total,
             "form": f"pipelined: every query of the step submitted at once (larger queries first) to the "
                     f"library's server ({a.pipe_builders} CST builder threads, {a.pipe_lanes} enumeration lanes); "
@@ -555,7 +565,7 @@ def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> dict:
 def profile_launch(a):
     """One batched step of the workload (every CST built, one launch) with the
     given tuning and nothing else, for rocprofv3 runs; prints one JSON line."""
-    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule)
+    S = Session(a.workload, a.mode, a.build_streams, a.max_queries, a.order_rule, a.exact_only)
     if a.tune:
         S.ctx.tune = json.loads(a.tune)
     if a.pipelined:
@@ -641,6 +651,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-queries", type=int, default=0)
+    ap.add_argument("--exact-only", action="store_true",
+                    help="only the queries whose stored count is the exact total (below the set's result limit), "
+                         "run without a limit")
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the default launch parameters")
     ap.add_argument("--served-requests", type=int, default=120,
                     help="requests in the short served-vs-plain comparison on the power-law workload (0: skip)")
@@ -681,7 +694,7 @@ def main():
         from synth import make_graph
 
         W = load_workload(a.workload)
-        queries, expected, limits, _ = workload_queries(W, a.max_queries)
+        queries, expected, limits, _ = workload_queries(W, a.max_queries, a.exact_only)
         if a.share:
             # the host share counts every embedding: only queries stored with
             # their exact total (no result limit) take part

@@ -91,6 +91,13 @@ def test_workload_queries_skip_inf_and_carry_limits():
     assert exp == [3, 5] and lim == [7, 7] and inf == 1 and [q.k for q in qs] == [2, 1]
     qs, exp, lim, inf = b.workload_queries(W, max_queries=1)
     assert exp == [3] and inf == 1
+    # exact totals only: a count that reached its limit is not a total
+    W["queries"].append({"qlabel": [0], "qedges": [], "count": 7, "limit": 7})
+    W["queries"].append({"qlabel": [1], "qedges": [], "count": 2, "limit": 0})
+    qs, exp, lim, inf = b.workload_queries(W, exact_only=True)
+    assert exp == [3, 5, 2] and lim == [0, 0, 0] and inf == 1
+    qs, exp, lim, inf = b.workload_queries(W)
+    assert exp == [3, 5, 7, 2] and lim == [7, 7, 7, 0]
 
 
 def test_cpu_baseline_samples_stored_queries_and_checks_finished_counts():

@@ -160,6 +160,33 @@ def test_small_config_lists_match_oracle_in_lds_mode():
             tuple(int(x) for x in row) for row in r.rows]
 
 
+def test_exact_r_mat_queries_in_lds_mode():
+    """The R-MAT set's queries whose stored count is the exact total (below the
+    set's result limit), cut into partition images (Algorithm 2) and counted in
+    one batched on-chip launch: every count equals the stored one and every
+    CST ran as images, none fell back to device memory."""
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c3")
+    g, G = _graph("c3", W, "lds")
+    rows = [(d, q) for d, q, lim in _counted(W) if not lim or d["count"] < lim]
+    assert len(rows) >= 50
+    c = ctx("lds")
+    c.tune = {"order_rule": _ORDER_RULE["c3"]}
+    try:
+        csts = [cstm.CST(c, G, q.qlabel, q.qedges) for _, q in rows]
+        parts = [cst.partition() for cst in csts]
+        got = cstm.batch_count(c, csts)
+        st = c.last_enum_stats()
+    finally:
+        c.tune = {"order_rule": 0}
+    for cst in csts:
+        cst.close()
+    say(f"c3 exact queries on chip: {len(rows)} CSTs, {sum(parts)} images, kernel {st['kernel_ms']:.1f} ms")
+    assert st["mode"] == cstm.MODE_LDS and st["launches"] == 1 and st["images"] == sum(parts)
+    assert got == [d["count"] for d, _ in rows]
+
+
 def test_deadline_stops_a_launch_and_the_context_recovers():
     """A 1 ms deadline, set from the host, ends the enumeration kernel early with ETIMEOUT."""
     from paper_2102_10768_amd import cstm
