@@ -310,11 +310,10 @@ cstm_status cstm_cst_candidates(const cstm_cst* cst, int32_t u, int32_t* out, in
  * DEVICE buffer rows[cap][k] (row[u] = data vertex of query vertex u, rows in
  * no particular order).
  *   limit        0: find every embedding.  > 0: *count_out is exactly
- *                min(total, limit), whatever order the search ran in; a
- *                search over the CST in device memory stops early once at
- *                least limit embeddings were found, while partition images
- *                are always counted in full (then clamped), so a limit does
- *                not shorten an on-chip launch.
+ *                min(total, limit), whatever order the search ran in; the
+ *                search stops early once at least limit embeddings were
+ *                found (over partition images: the images not yet started
+ *                are skipped, every started one is counted in full).
  *   deadline_s   > 0: stop the launch after this many seconds and return
  *                CSTM_ETIMEOUT (nothing is reported); <= 0: the context's
  *                tune.deadline_ms applies.
@@ -327,9 +326,8 @@ cstm_status cstm_enumerate(cstm_cst* cst, int list, uint64_t limit, int32_t* row
 /* Count the embeddings of many CSTs in one persistent launch that draws work
  * from a device queue (the batched form).  limits (host, may be NULL): per
  * CST, 0 = count all, > 0 = counts_out[i] is exactly min(total_i, limits[i])
- * (a CST searched in device memory stops once it has that many; partition
- * images are counted in full, as for cstm_enumerate).  counts_out[nq] is a
- * host array. */
+ * (that CST's search stops once it has that many, as for cstm_enumerate).
+ * counts_out[nq] is a host array. */
 cstm_status cstm_batch_enumerate(cstm_ctx* ctx, int32_t nq, cstm_cst* const* csts, const uint64_t* limits,
                                  uint64_t* counts_out, void* stream);
 

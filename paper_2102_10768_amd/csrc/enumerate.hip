@@ -46,6 +46,8 @@ struct EnumArgs {
     unsigned long long* stats;  // [images, bytes, N, M, F] or nullptr
     unsigned long long* stop;   // set to 2 once the deadline has passed
     uint64_t deadline;          // s_memrealtime ticks (100 MHz) after the start; 0 = none
+    const unsigned long long* limits;  // per query slot: skip its images once its count reaches this
+                                       // (0: none); nullptr: no limits
 };
 
 // Deadline check, the same answer in every lane of the wavefront: true once
@@ -287,16 +289,32 @@ __global__ void k_enumerate(EnumArgs A) {
     uint8_t* img = (uint8_t*)smem_u4;
     __shared__ int64_t s_blob;
     __shared__ unsigned int s_next;
+    __shared__ int s_skip;
     const int lane = lane_id();
     const uint64_t t_end = __builtin_amdgcn_s_memrealtime() + A.deadline;
     for (;;) {
         if (threadIdx.x == 0) {
             const bool stop = A.deadline && __hip_atomic_load(A.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_blob = stop ? A.n_blobs : (int64_t)atomicAdd(A.head, 1u);
+            const int64_t nb = stop ? A.n_blobs : (int64_t)atomicAdd(A.head, 1u);
+            // Counts grow only as images finish, so once a query's count has
+            // reached its limit the result is min(total, limit) = limit
+            // whatever its remaining images hold: they are skipped.
+            int skip = 0;
+            if (A.limits && nb < A.n_blobs) {
+                const int q = A.qids ? A.qids[nb] : 0;
+                const unsigned long long lim = A.limits[q];
+                skip = lim && __hip_atomic_load(A.counts + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lim;
+            }
+            s_blob = nb;
+            s_skip = skip;
         }
         __syncthreads();
         const int64_t b = s_blob;
         if (b >= A.n_blobs) break;
+        if (s_skip) {
+            __syncthreads();  // every thread has read s_blob and s_skip before thread 0 writes them again
+            continue;
+        }
         const uint8_t* src = (const uint8_t*)A.blobs[b];
         const uint32_t bytes = ((const BlobHdr*)src)->bytes;
         for (uint32_t o = threadIdx.x * 16u; o < bytes; o += blockDim.x * 16u)
@@ -362,6 +380,24 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     A.stats = ctx->tune.collect_stats ? work + 1 : nullptr;
     A.stop = work + 6;
     A.deadline = opt.deadline_ms > 0 ? 100ull * 1000 * (uint64_t)opt.deadline_ms : 0;
+    // per-slot limits (the caller's array is indexed by slot, as the counts are)
+    std::vector<unsigned long long> hlim;
+    A.limits = nullptr;
+    if (opt.limits) {
+        int32_t nslots = 0;
+        for (int q = 0; q < nq; ++q) nslots = std::max(nslots, slot[q] + 1);
+        hlim.assign(nslots, 0ull);
+        bool any = false;
+        for (int q = 0; q < nq; ++q) {
+            hlim[slot[q]] = opt.limits[slot[q]];
+            any |= hlim[slot[q]] != 0;
+        }
+        if (any) {
+            unsigned long long* dlim = mem.get_n<unsigned long long>(nslots);
+            HIP_TRY(hipMemcpyAsync(dlim, hlim.data(), (size_t)nslots * 8, hipMemcpyHostToDevice, s));
+            A.limits = dlim;
+        }
+    }
     const int waves = ctx->tune.waves_per_wg;
     const size_t lds = (size_t)cstm_align16(max_blob);
     static std::once_flag attr_once;
@@ -456,7 +492,7 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
     if (st_out) *st_out = st;
     for (int q = 0; q < nq; ++q) {
         counts_host[q] = h[q];
-        // a launch passes a limit before it stops, and LDS mode counts everything
+        // a launch passes a limit before it stops (an on-chip launch finishes every image it started)
         if (o.limits && o.limits[q] && counts_host[q] > o.limits[q]) counts_host[q] = o.limits[q];
     }
     if (rows_written) *rows_written = std::min<uint64_t>(h[nq], cap);

@@ -187,6 +187,48 @@ def test_exact_r_mat_queries_in_lds_mode():
     assert got == [d["count"] for d, _ in rows]
 
 
+def test_on_chip_limits_give_min_of_total_and_limit_and_skip_images():
+    """Per-query limits over partition images: every count is exactly
+    min(total, limit); once a CST's count has reached its limit, its images not
+    yet started are skipped, so a limit of 1 on the CST with the most images
+    runs fewer images than it holds (256 workgroups take images at once)."""
+    from paper_2102_10768_amd import cstm
+
+    W = _load("c3")
+    g, G = _graph("c3", W, "lds")
+    rows = [(d, q) for d, q, lim in _counted(W) if not lim or d["count"] < lim]
+    totals = [d["count"] for d, _ in rows]
+    limits = [[0, 1, t // 2, t, t + 1][i % 5] for i, t in enumerate(totals)]
+    c = ctx("lds")
+    before = c.tune
+    c.tune = {"order_rule": _ORDER_RULE["c3"]}
+    csts = []
+    try:
+        for _, q in rows:
+            csts.append(cstm.CST(c, G, q.qlabel, q.qedges))
+        parts = [cst.partition() for cst in csts]
+        got = cstm.batch_count(c, csts, limits=limits)
+        st_b = c.last_enum_stats()
+        big = max(range(len(csts)), key=lambda i: parts[i])
+        c.tune = {"wgs_per_cu": 1}
+        one = csts[big].count(limit=1)
+        st_1 = c.last_enum_stats()
+        whole = csts[big].count()
+        st_w = c.last_enum_stats()
+    finally:
+        c.tune = {"order_rule": before["order_rule"], "wgs_per_cu": before["wgs_per_cu"]}
+        for cst in csts:
+            cst.close()
+    say(f"limits on chip: batched {st_b['images']} of {sum(parts)} images; "
+        f"limit 1 on {parts[big]} images ran {st_1['images']}")
+    assert got == [t if not lim else min(t, lim) for t, lim in zip(totals, limits)]
+    assert st_b["mode"] == cstm.MODE_LDS and st_b["images"] <= sum(parts)
+    assert one == 1 and whole == totals[big]
+    assert st_w["images"] == parts[big]
+    if parts[big] > 256:  # more images than workgroups
+        assert st_1["images"] < parts[big]
+
+
 def test_deadline_stops_a_launch_and_the_context_recovers():
     """A 1 ms deadline, set from the host, ends the enumeration kernel early with ETIMEOUT."""
     from paper_2102_10768_amd import cstm
