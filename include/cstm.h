@@ -247,8 +247,8 @@ cstm_status cstm_graph_label_edges(const cstm_graph* g, uint64_t* out, int64_t c
  *   k in 1..32, qlabel[k] >= 0, qedges[2*m_q] (host arrays): undirected query
  *   edges as id pairs; q must be connected, with no self-loop or duplicate edge.
  * Candidates pass the label/degree filter; the BFS tree t_q is rooted at the
- * vertex minimising #candidates / query degree; the matching order is the
- * path-based order of Section V-B. */
+ * vertex minimising #candidates / query degree; the matching order follows
+ * tune.order_rule (default: the path-based order of Section V-B). */
 cstm_status cstm_cst_build(cstm_ctx* ctx, const cstm_graph* g, int32_t k, const int32_t* qlabel,
                            int32_t m_q, const int32_t* qedges, void* stream, cstm_cst** out);
 
@@ -268,7 +268,8 @@ cstm_status cstm_cst_build_ordered(cstm_ctx* ctx, const cstm_graph* g, int32_t k
  * its build-time tables, from the label index alone.  #C(u) is at most the
  * number of vertices passing the label and degree filter, and a candidate edge
  * list holds each data edge at most once, so the summed degrees of either
- * endpoint's filtered candidates bound its entries.  Host-only: no device work,
+ * endpoint's filtered candidates, and the edges between the two labels
+ * (cstm_graph_label_edges), bound its entries.  Host-only: no device work,
  * no allocation.  The context's block cache rounds each request up to a power
  * of two (up to 256 MB), so device use can reach twice this figure.  Meant for
  * admission control before building.  CSTM_EINVAL on a malformed query. */
@@ -387,11 +388,10 @@ cstm_status cstm_enumerate_shared(cstm_cst* cst, double delta, int64_t n_runs, i
  * queries arrive one at a time and share the GPU).  The server admits
  * requests in arrival order while the device-memory bound of their CST
  * builds (cstm_cst_estimate, doubled for the block cache's rounding) fits
- * mem_budget; once a CST is built its charge drops to twice the device
- * bytes the CST holds (the build's temporaries are freed); builds admitted
- * CSTs on
- * `builders` threads, each with its own
- * stream; and gives every built CST to the next free enumeration lane, which
+ * mem_budget (once a CST is built its charge drops to twice the device
+ * bytes the CST holds, as the build's temporaries are freed); builds admitted
+ * CSTs on `builders` threads, each with its own stream; and gives every
+ * built CST to the next free enumeration lane, which
  * counts all CSTs built so far (up to max_batch) in one persistent launch on
  * its own stream, reading the CSTs from device memory whatever the context's
  * enum_mode (so no partition images exceed what admission charged).  Each
