@@ -93,10 +93,12 @@ typedef void (*cstm_free_fn)(void* ptr, void* user);
  *                      interval halves back to this after a donation and
  *                      doubles, up to hbm_donate_period, after a check that
  *                      finds no wavefront waiting.
- *   hbm_flat_max       HBM mode: the last level is expanded as one flat list
- *                      over all surviving parents when their candidate lists
- *                      sum to at most this many entries (default 2048;
- *                      negative: never).
+ *   hbm_flat_max       HBM mode: the next level is expanded as one flat list
+ *                      over all surviving parents of a chunk when their
+ *                      candidate lists sum to at most this many entries, if it
+ *                      is the last level, or the second-to-last while the last
+ *                      is counted by list lengths (last_level_sum) (default
+ *                      2048; negative: never).
  *   hbm_donate_last_min HBM mode: smallest remainder of the last level a
  *                      wavefront hands to a waiting one (default 4096).
  *   last_level_sum     HBM mode, counting only: when the last query vertex of
