@@ -74,7 +74,7 @@ struct GArgs {
     uint64_t deadline;          // absolute s_memrealtime tick to stop at (0 = none)
     int donate_period;          // longest interval in chunks between donation checks (<= 0: never donate)
     int donate_min;             // shortest such interval
-    int64_t flat_max;           // expand the next level flattened when the survivors' lists sum to at most this
+    int64_t flat_max;           // expand the last level flattened when the survivors' lists sum to at most this
     int64_t donate_last_min;    // smallest last-level remainder worth donating
     int last_sum;               // > 0: count an unconstrained last level by list lengths
     const unsigned long long* limits;  // per query: stop once its count reaches this (0: none); nullptr: none
