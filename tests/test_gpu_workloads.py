@@ -191,7 +191,8 @@ def test_on_chip_limits_give_min_of_total_and_limit_and_skip_images():
     """Per-query limits over partition images: every count is exactly
     min(total, limit); once a CST's count has reached its limit, its images not
     yet started are skipped, so a limit of 1 on the CST with the most images
-    runs fewer images than it holds (256 workgroups take images at once)."""
+    runs fewer images than it holds (256 workgroups take images at once); a
+    listing under a limit returns exactly that many distinct embeddings."""
     from paper_2102_10768_amd import cstm
 
     W = _load("c3")
@@ -215,6 +216,8 @@ def test_on_chip_limits_give_min_of_total_and_limit_and_skip_images():
         st_1 = c.last_enum_stats()
         whole = csts[big].count()
         st_w = c.last_enum_stats()
+        n_l, rows_l = csts[big].list(4096, limit=100)
+        rows_l = rows_l.cpu().numpy()
     finally:
         c.tune = {"order_rule": before["order_rule"], "wgs_per_cu": before["wgs_per_cu"]}
         for cst in csts:
@@ -225,6 +228,10 @@ def test_on_chip_limits_give_min_of_total_and_limit_and_skip_images():
     assert st_b["mode"] == cstm.MODE_LDS and st_b["images"] <= sum(parts)
     assert one == 1 and whole == totals[big]
     assert st_w["images"] == parts[big]
+    # listing under a limit: exactly min(total, limit) distinct embeddings
+    assert n_l == min(totals[big], 100) and rows_l.shape[0] == n_l
+    assert len({tuple(r) for r in rows_l.tolist()}) == n_l
+    _check_rows(g, rows[big][1], rows_l)
     if parts[big] > 256:  # more images than workgroups
         assert st_1["images"] < parts[big]
 
