@@ -5,8 +5,10 @@ CPU oracle or, for tree queries with pairwise-distinct labels, from the exact
 labelled tree DP.  A query stored with a result limit L counts min(total, L);
 a query the oracle could not finish within its screen (INF, no stored count)
 is not run.  The counts are compared in the launch configuration the benchmark
-times (one query per launch) and in the batched form.  Listings are sampled
-and every sampled row is checked to be an embedding.
+times (one query per launch) and in the batched form, and the R-MAT set's
+exactly counted queries also as partition images on chip (with and without
+limits).  Listings are sampled and every sampled row is checked to be an
+embedding.
 """
 
 from __future__ import annotations
