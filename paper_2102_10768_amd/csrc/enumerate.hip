@@ -24,7 +24,12 @@
 // Work inside a workgroup is shared at the granularity of (root, first child)
 // pairs handed out 64 at a time from an LDS counter.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <exception>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -438,14 +443,62 @@ void cstm_enumerate_lds_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, const 
     CSTM_REQUIRE(h[6] != 2, CSTM_ETIMEOUT, "enumeration stopped at the deadline");
 }
 
+// Partition, at the context's budget, the CSTs an LDS launch meets
+// unpartitioned; fits[i] = 0 when the images of cut[i] would replicate it
+// beyond max_replication (that CST stays in HBM).  Algorithm 2 runs on each
+// CST's own stream, and its first round is a single workgroup, so several
+// host threads cut different CSTs at once to keep the GPU busy.
+static void partition_for_lds(cstm_ctx* ctx, cstm_cst* const* csts, const std::vector<int>& cut,
+                              std::vector<char>& fits) {
+    constexpr size_t kPartThreads = 8;
+    const cstm_tune T = ctx->tune;
+    fits.assign(cut.size(), 1);
+    auto cut_one = [&](size_t i) {
+        cstm_cst* c = csts[cut[i]];
+        const uint64_t cap =
+            T.max_replication > 0 ? (uint64_t)T.max_replication * std::max<uint64_t>(c->bytes, 4096) : 0;
+        fits[i] = cstm_partition_run(c, 0, T.max_list_len, cap) ? 1 : 0;
+    };
+    const size_t n_threads = std::min(cut.size(), kPartThreads);
+    if (n_threads <= 1) {
+        for (size_t i = 0; i < cut.size(); ++i) cut_one(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::mutex err_mu;
+    std::exception_ptr err;
+    auto worker = [&] {
+        try {
+            HIP_TRY(hipSetDevice(ctx->device));
+            for (size_t i; (i = next.fetch_add(1)) < cut.size();) cut_one(i);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(err_mu);
+            if (!err) err = std::current_exception();
+            next.store(cut.size());  // the other threads take no further CST
+        }
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (size_t t = 0; t < n_threads; ++t) pool.emplace_back(worker);
+    } catch (...) {
+        next.store(cut.size());
+        for (auto& th : pool) th.join();
+        throw;
+    }
+    for (auto& th : pool) th.join();
+    if (err) std::rethrow_exception(err);
+}
+
 // Enumerate nq CSTs: pick LDS images or the HBM-resident CST per the tuning,
 // run at most one launch of each kind, and return per-CST counts.
 void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, int32_t* rows, uint64_t cap,
                         uint64_t* counts_host, uint64_t* rows_written, const EnumOpts& o, hipStream_t s,
                         cstm_enum_stats* st_out) {
     const cstm_tune T = ctx->tune;
-    std::vector<cstm_cst*> lds_q, hbm_q;
-    std::vector<int> lds_slot, hbm_slot;
+    std::vector<int> mode_of(nq, -1);  // -1: empty CST, nothing to launch
+    std::vector<int> cut;              // LDS-mode CSTs still to partition, each CST once
+    std::vector<int> cut_of(nq, -1);   // index into cut of the CST at q
+    std::unordered_map<const cstm_cst*, int> seen;
     for (int q = 0; q < nq; ++q) {
         cstm_cst* c = csts[q];
         if (c->empty) continue;
@@ -457,16 +510,27 @@ void cstm_enumerate_run(cstm_ctx* ctx, int nq, cstm_cst* const* csts, int list, 
             mode = c->partitioned ? CSTM_MODE_LDS : CSTM_MODE_HBM;
         }
         if (mode == CSTM_MODE_LDS && !c->partitioned) {
-            // partition at the context's budget, unless the images would replicate
-            // the CST beyond max_replication: then the CST stays in HBM
-            uint64_t cap = T.max_replication > 0 ? (uint64_t)T.max_replication * std::max<uint64_t>(c->bytes, 4096) : 0;
-            if (!cstm_partition_run(c, 0, T.max_list_len, cap)) mode = CSTM_MODE_HBM;
+            auto it = seen.emplace(c, (int)cut.size()).first;
+            if (it->second == (int)cut.size()) cut.push_back(q);
+            cut_of[q] = it->second;
         }
-        if (mode == CSTM_MODE_LDS) {
-            lds_q.push_back(c);
+        mode_of[q] = mode;
+    }
+    if (!cut.empty()) {
+        std::vector<char> fits;
+        partition_for_lds(ctx, csts, cut, fits);
+        for (int q = 0; q < nq; ++q)
+            if (cut_of[q] >= 0 && !fits[cut_of[q]]) mode_of[q] = CSTM_MODE_HBM;
+    }
+    std::vector<cstm_cst*> lds_q, hbm_q;
+    std::vector<int> lds_slot, hbm_slot;
+    for (int q = 0; q < nq; ++q) {
+        if (mode_of[q] < 0) continue;
+        if (mode_of[q] == CSTM_MODE_LDS) {
+            lds_q.push_back(csts[q]);
             lds_slot.push_back(q);
         } else {
-            hbm_q.push_back(c);
+            hbm_q.push_back(csts[q]);
             hbm_slot.push_back(q);
         }
     }
