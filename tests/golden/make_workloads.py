@@ -36,8 +36,6 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.dirname(HERE))
 
-import numpy as np  # noqa: E402
-
 import oracle  # noqa: E402
 import closed_forms as cf  # noqa: E402
 from synth import make_graph, query_set  # noqa: E402

@@ -5,7 +5,6 @@ No compute call is made here (there is no GPU on the build host).
 
 from __future__ import annotations
 
-import ctypes
 import os
 import re
 

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import bruteforce
 import closed_forms as cf
-from synth import Graph, Query, make_graph, query_set, random_walk_query
+from synth import Graph, Query, make_graph, query_set
 
 
 # ---------------------------------------------------------------- helpers
