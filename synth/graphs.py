@@ -113,16 +113,6 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, log=None) -> tuple[np.n
     return row_ptr, col
 
 
-def _permute(n: int, row_ptr: np.ndarray, col: np.ndarray, perm: np.ndarray):
-    """Relabel vertex v as perm[v]; returns a new sorted CSR."""
-    deg = np.diff(row_ptr)
-    src = np.repeat(np.arange(n, dtype=np.int64), deg)
-    a = perm[src].astype(np.int64)
-    b = perm[col.astype(np.int64)].astype(np.int64)
-    keep = a < b
-    return csr_from_edges(n, a[keep], b[keep])
-
-
 def erdos_renyi(n: int, p: float, seed: int):
     """G(n, p): every unordered pair is an edge independently with probability p.
 
