@@ -488,7 +488,9 @@ bool cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list, uint64_t
     c->max_blob = 0;
     c->part_budget = budget;
     c->part_max_list = max_list;
-    c->partitioned = true;
+    // marked partitioned only once every image is written: a run that throws
+    // leaves the CST unpartitioned, never partitioned with missing images
+    c->partitioned = c->empty;
     if (c->empty) return true;
 
     const int k = c->k;
@@ -644,6 +646,7 @@ bool cstm_partition_run(cstm_cst* c, uint64_t budget, int32_t max_list, uint64_t
     c->mem.release(spec_b);
     c->mem.release(scratch);
     c->mem.release(dc);
+    c->partitioned = true;
     return true;
 }
 
